@@ -1,0 +1,231 @@
+"""FP64 CPU oracle of the directionally unsplit hydro schemes (arXiv:1103.3373, Sec. 2).
+
+TEST INFRASTRUCTURE ONLY.  The oracle is the slow, plain reference that the
+HIP library is checked against.  Only the test suite, the smoke check and the
+CPU-baseline leg of the benchmark may import it; the product path never does.
+It shares no code with the HIP library: the numerics live in ``oracle.cpp``,
+this module only compiles it and marshals numpy arrays through ctypes.
+
+Every array is float64 and C-contiguous.  Layouts follow the paper's flattened
+``[var][z][y][x]`` order (Sec. 3.1), variables (rho, mx, my, mz, E).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.cpp")
+LIB = os.path.join(_HERE, "liboracle.so")
+LIB_COUNT = os.path.join(_HERE, "liboracle_count.so")
+
+MHM, VL, CTU = 0, 1, 2
+PLM, PPM = 0, 1
+ROE, HLLC, HLLE, EXACT = 0, 1, 2, 3
+GMINMOD, VANLEER, VANALBADA, HYBRID = 0, 1, 2, 3
+F_CHAR, F_FLUX_MID, F_ROE_FB_HLLC = 0x02, 0x04, 0x10
+
+
+def build(force: bool = True) -> None:
+    """Compile the oracle (plain and op-counting builds) with g++."""
+    flags = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-std=c++17"]
+    for out, extra in ((LIB, []), (LIB_COUNT, ["-DORACLE_COUNT_OPS"])):
+        if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+            tmp = out + ".tmp"
+            subprocess.check_call(["g++", *flags, *extra, _SRC, "-o", tmp])
+            os.replace(tmp, out)
+
+
+_libs: dict[str, ctypes.CDLL] = {}
+
+
+def _lib(counting: bool = False) -> ctypes.CDLL:
+    path = LIB_COUNT if counting else LIB
+    if path in _libs:
+        return _libs[path]
+    if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+        build(force=False)
+    L = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    i, d = ctypes.c_int, ctypes.c_double
+    L.oracle_step_box.argtypes = [P, P, i, i, i, d, d, d, i, i, i, i, i]
+    L.oracle_step_box.restype = i
+    L.oracle_solve_groups.argtypes = [P, P, P, i, i, d, d, d, i, i, i, i, i]
+    L.oracle_solve_groups.restype = i
+    L.oracle_fill_ghosts_periodic.argtypes = [P, i, i, i, i, P]
+    L.oracle_fill_ghosts_periodic.restype = i
+    L.oracle_cfl_dt.argtypes = [P, ctypes.c_long, ctypes.c_long, d, d, d]
+    L.oracle_cfl_dt.restype = d
+    L.oracle_conserved_sums.argtypes = [P, ctypes.c_long, ctypes.c_long, d, P]
+    L.oracle_conserved_sums.restype = None
+    L.oracle_riemann_flux.argtypes = [P, P, i, d, i, i, P]
+    L.oracle_riemann_flux.restype = i
+    L.oracle_roe_ok.argtypes = [P, P, d]
+    L.oracle_roe_ok.restype = i
+    L.oracle_exact_riemann.argtypes = [P, P, d, P, P, i, P]
+    L.oracle_exact_riemann.restype = i
+    L.oracle_limiter.argtypes = [d, d, i]
+    L.oracle_limiter.restype = d
+    L.oracle_slope.argtypes = [P, P, P, i, d, i, i, P]
+    L.oracle_slope.restype = None
+    L.oracle_ppm_edge.argtypes = [P, P, P, P, P]
+    L.oracle_ppm_edge.restype = None
+    L.oracle_char.argtypes = [P, P, d, P, P]
+    L.oracle_char.restype = None
+    L.oracle_ghost_width.argtypes = [i, i]
+    L.oracle_ghost_width.restype = i
+    L.oracle_get_stats.argtypes = [P]
+    L.oracle_get_stats.restype = None
+    L.oracle_reset_stats.argtypes = []
+    L.oracle_reset_stats.restype = None
+    L.oracle_get_ops.argtypes = []
+    L.oracle_get_ops.restype = ctypes.c_ulonglong
+    L.oracle_reset_ops.argtypes = []
+    L.oracle_reset_ops.restype = None
+    _libs[path] = L
+    return L
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def ghost_width(scheme: int, recon: int) -> int:
+    """Minimum ghost width of the scheme / reconstruction stencil."""
+    return _lib().oracle_ghost_width(scheme, recon)
+
+
+def step_box(U, dt, dh, gamma, scheme, recon, riemann, limiter, flags=0, counting=False) -> np.ndarray:
+    """One step on a periodic box U[5][nz][ny][nx]."""
+    U = _f64(U)
+    assert U.ndim == 4 and U.shape[0] == 5
+    out = np.empty_like(U)
+    nz, ny, nx = U.shape[1:]
+    rc = _lib(counting).oracle_step_box(_p(U), _p(out), nx, ny, nz, dt, dh, gamma, scheme, recon, riemann,
+                                        limiter, flags)
+    if rc != 0:
+        raise ValueError(f"oracle_step_box failed ({rc})")
+    return out
+
+
+def solve_groups(G, g, dt, dh, gamma, scheme, recon, riemann, limiter, flags=0, want_flux=False,
+                 counting=False):
+    """One step on padded groups G[n][5][N][N][N] -> (out[n][5][16][16][16], flux or None)."""
+    G = _f64(G)
+    n = G.shape[0]
+    N = 16 + 2 * g
+    assert G.shape == (n, 5, N, N, N), G.shape
+    out = np.empty((n, 5, 16, 16, 16))
+    nf = 3 if flags & F_FLUX_MID else 2
+    flux = np.empty((n, 3, nf, 5, 16, 16)) if want_flux else None
+    rc = _lib(counting).oracle_solve_groups(_p(G), _p(out), _p(flux) if want_flux else None, n, g, dt, dh,
+                                            gamma, scheme, recon, riemann, limiter, flags)
+    if rc != 0:
+        raise ValueError(f"oracle_solve_groups failed ({rc})")
+    return out, flux
+
+
+def fill_ghosts_periodic(box, g) -> np.ndarray:
+    """box[5][nz][ny][nx] -> padded groups [G][5][16+2g]^3 (periodic wrap)."""
+    box = _f64(box)
+    nz, ny, nx = box.shape[1:]
+    N = 16 + 2 * g
+    n = (nx // 16) * (ny // 16) * (nz // 16)
+    out = np.empty((n, 5, N, N, N))
+    rc = _lib().oracle_fill_ghosts_periodic(_p(box), nx, ny, nz, g, _p(out))
+    if rc != 0:
+        raise ValueError("oracle_fill_ghosts_periodic failed")
+    return out
+
+
+def cfl_dt(U, dh, gamma, cfl) -> float:
+    """dt = cfl*dh / max_cells max_d(|v_d| + c); U is [..., 5, cells...] blocks."""
+    U = _f64(U)
+    if U.ndim == 4:
+        nb, ncell = 1, U[0].size
+    else:
+        nb, ncell = U.shape[0], U[0, 0].size
+    return _lib().oracle_cfl_dt(_p(U), nb, ncell, dh, gamma, cfl)
+
+
+def conserved_sums(U, dh) -> np.ndarray:
+    U = _f64(U)
+    if U.ndim == 4:
+        nb, ncell = 1, U[0].size
+    else:
+        nb, ncell = U.shape[0], U[0, 0].size
+    s = np.empty(5)
+    _lib().oracle_conserved_sums(_p(U), nb, ncell, dh, _p(s))
+    return s
+
+
+def riemann_flux(WL, WR, d, gamma, riemann, flags=0) -> np.ndarray:
+    WL, WR = _f64(WL), _f64(WR)
+    F = np.empty(5)
+    rc = _lib().oracle_riemann_flux(_p(WL), _p(WR), d, gamma, riemann, flags, _p(F))
+    if rc != 0:
+        raise ValueError("oracle_riemann_flux failed")
+    return F
+
+
+def roe_ok(WL, WR, gamma) -> bool:
+    return bool(_lib().oracle_roe_ok(_p(_f64(WL)), _p(_f64(WR)), gamma))
+
+
+def exact_riemann(WL, WR, gamma, xi=()):
+    """Exact Riemann problem along x: (star dict, W[len(xi)][5])."""
+    WL, WR = _f64(WL), _f64(WR)
+    xi = _f64(np.atleast_1d(np.asarray(xi, dtype=np.float64)))
+    star = np.empty(5)
+    W = np.empty((max(len(xi), 1), 5))
+    _lib().oracle_exact_riemann(_p(WL), _p(WR), gamma, _p(star), _p(xi), len(xi), _p(W))
+    return ({"p": star[0], "u": star[1], "rhoL": star[2], "rhoR": star[3], "ok": bool(star[4])},
+            W[:len(xi)])
+
+
+def limiter(dl, dr, lim) -> float:
+    return _lib().oracle_limiter(float(dl), float(dr), lim)
+
+
+def slope(wm, w0, wp, d, gamma, lim, flags=0) -> np.ndarray:
+    s = np.empty(5)
+    _lib().oracle_slope(_p(_f64(wm)), _p(_f64(w0)), _p(_f64(wp)), d, gamma, lim, flags, _p(s))
+    return s
+
+
+def ppm_edge(wa, wb, sa, sb) -> np.ndarray:
+    e = np.empty(5)
+    _lib().oracle_ppm_edge(_p(_f64(wa)), _p(_f64(wb)), _p(_f64(sa)), _p(_f64(sb)), _p(e))
+    return e
+
+
+def char_roundtrip(w, dw, gamma):
+    """(L dw, R L dw) at frame-ordered state w."""
+    a, b = np.empty(5), np.empty(5)
+    _lib().oracle_char(_p(_f64(w)), _p(_f64(dw)), gamma, _p(a), _p(b))
+    return a, b
+
+
+def stats(counting=False) -> dict:
+    s = (ctypes.c_longlong * 4)()
+    _lib(counting).oracle_get_stats(ctypes.cast(s, ctypes.c_void_p))
+    return {"solves": s[0], "roe_fail": s[1], "floor_hits": s[2], "exact_fail": s[3]}
+
+
+def reset_stats(counting=False) -> None:
+    _lib(counting).oracle_reset_stats()
+
+
+def ops() -> int:
+    return int(_lib(True).oracle_get_ops())
+
+
+def reset_ops() -> None:
+    _lib(True).oracle_reset_ops()

@@ -1,0 +1,586 @@
+"""Pins of the FP64 oracle against what the mathematics and the paper fix.
+
+The oracle is the reference the HIP path is compared with, so it is first
+checked against things other than itself: a published exact solution, the
+Rankine-Hugoniot and isentropic relations, conservation, free-stream and
+contact invariance, symmetry (paper Sec. 1: unsplit schemes keep spatial
+symmetry), convergence order, limiter and reconstruction identities, the
+Riemann-solve counts per cell (Sec. 3.2: three for MHM, six for VL and CTU),
+Roe failure and HLLE positivity (Sec. 2), and the linear stability factors
+of the first-order limits.
+"""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+from paper_1103_3373_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+SCHEMES = (0, 1, 2)
+RECONS = (0, 1)
+SOLVERS = (0, 1, 2)
+LIMITERS = (0, 1, 2, 3)
+CHAR = 0x02
+
+
+def _golden(name):
+    vals = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                k, v = line.split()
+                vals[k] = float(v)
+    return vals
+
+
+def _random_smooth_box(n, gamma, seed, amp=0.2, ny=None, nz=None):
+    """Smooth positive random state (low Fourier modes) on a periodic box."""
+    ny = n if ny is None else ny
+    nz = n if nz is None else nz
+    rng = np.random.default_rng(seed)
+    x = (np.arange(n) + 0.5) / n
+    y = (np.arange(ny) + 0.5) / ny
+    z = (np.arange(nz) + 0.5) / nz
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    fields = []
+    for _ in range(5):
+        f = np.zeros_like(X)
+        for _ in range(3):
+            k = rng.integers(-2, 3, size=3)
+            ph = rng.uniform(0, 2 * np.pi)
+            f += rng.uniform(-1, 1) * np.cos(2 * np.pi * (k[0] * X + k[1] * Y + k[2] * Z) + ph)
+        fields.append(f)
+    rho = 1.0 + amp * fields[0] / 3
+    p = 1.0 + amp * fields[4] / 3
+    return W.primitive_to_conserved(rho, amp * fields[1], amp * fields[2], amp * fields[3], p, gamma)
+
+
+# ---------------------------------------------------------------------------
+# P1: exact Riemann solver
+# ---------------------------------------------------------------------------
+def test_exact_sod_matches_published_table(oracle):
+    g = _golden("sod_exact_toro.txt")
+    star, _ = oracle.exact_riemann([1.0, 0, 0, 0, 1.0], [0.125, 0, 0, 0, 0.1], g["gamma"])
+    assert star["ok"]
+    for key, ref in (("p", "p_star"), ("u", "u_star"), ("rhoL", "rho_star_L"), ("rhoR", "rho_star_R")):
+        assert abs(star[key] - g[ref]) <= 6e-6, (key, star[key], g[ref])
+
+
+@pytest.mark.parametrize("gamma", [1.4, 5.0 / 3.0])
+def test_exact_sod_rankine_hugoniot_and_isentrope(oracle, gamma):
+    """Shock: mass, momentum and energy fluxes continuous in the shock frame.
+    Rarefaction: p/rho^gamma and u + 2c/(gamma-1) constant across the fan."""
+    rL, pL, rR, pR = 1.0, 1.0, 0.125, 0.1
+    star, _ = oracle.exact_riemann([rL, 0, 0, 0, pL], [rR, 0, 0, 0, pR], gamma)
+    ps, us, rsl, rsr = star["p"], star["u"], star["rhoL"], star["rhoR"]
+    # Right-moving shock: speed from mass conservation, then momentum and energy.
+    S = (rsr * us - rR * 0.0) / (rsr - rR)
+    m1 = rR * (0.0 - S)
+    m2 = rsr * (us - S)
+    assert abs(m1 - m2) < 1e-12
+    mom1 = rR * (0.0 - S) ** 2 + pR
+    mom2 = rsr * (us - S) ** 2 + ps
+    assert abs(mom1 - mom2) < 1e-12
+    h1 = gamma / (gamma - 1) * pR / rR + 0.5 * (0.0 - S) ** 2
+    h2 = gamma / (gamma - 1) * ps / rsr + 0.5 * (us - S) ** 2
+    assert abs(h1 - h2) < 1e-12
+    # Left rarefaction: isentropic and Riemann invariant.
+    assert abs(pL / rL ** gamma - ps / rsl ** gamma) < 1e-12
+    cL, cs = np.sqrt(gamma * pL / rL), np.sqrt(gamma * ps / rsl)
+    assert abs((0.0 + 2 * cL / (gamma - 1)) - (us + 2 * cs / (gamma - 1))) < 1e-12
+    # Samples: inside the fan the state is isentropic with the same invariant.
+    xi = np.linspace(-cL + 1e-3, us - cs - 1e-3, 7)
+    _, Ws = oracle.exact_riemann([rL, 0, 0, 0, pL], [rR, 0, 0, 0, pR], gamma, xi)
+    c_fan = np.sqrt(gamma * Ws[:, 4] / Ws[:, 0])
+    np.testing.assert_allclose(Ws[:, 4] / Ws[:, 0] ** gamma, pL / rL ** gamma, rtol=1e-12)
+    np.testing.assert_allclose(Ws[:, 1] + 2 * c_fan / (gamma - 1), 2 * cL / (gamma - 1), rtol=1e-12)
+    np.testing.assert_allclose(Ws[:, 1] - c_fan, xi, atol=1e-12)  # C- characteristics fan
+
+
+def test_exact_riemann_symmetric_and_trivial(oracle):
+    g = 1.4
+    star, _ = oracle.exact_riemann([1.0, -1.0, 0, 0, 1.0], [1.0, 1.0, 0, 0, 1.0], g)
+    assert abs(star["u"]) < 1e-14 and star["p"] < 1.0
+    star, W1 = oracle.exact_riemann([0.7, 0.3, 0.1, -0.2, 2.0], [0.7, 0.3, 0.1, -0.2, 2.0], g, [0.0])
+    np.testing.assert_allclose(W1[0], [0.7, 0.3, 0.1, -0.2, 2.0], rtol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# P8: Riemann solver consistency
+# ---------------------------------------------------------------------------
+def _phys_flux_x(Wp, gamma):
+    r, u, v, w, p = Wp
+    E = p / (gamma - 1) + 0.5 * r * (u * u + v * v + w * w)
+    return np.array([r * u, r * u * u + p, r * u * v, r * u * w, u * (E + p)])
+
+
+@pytest.mark.parametrize("rs", [0, 1, 2, 3])
+def test_riemann_consistency(oracle, rs):
+    g = 1.4
+    Wst = np.array([1.3, 0.4, -0.2, 0.7, 2.1])
+    np.testing.assert_allclose(oracle.riemann_flux(Wst, Wst, 0, g, rs), _phys_flux_x(Wst, g), rtol=1e-13,
+                               atol=1e-14)
+    # Supersonic to the right: the upwind flux is the left physical flux.
+    L, R = np.array([1.0, 3.0, 0.1, 0.0, 1.0]), np.array([0.8, 2.9, -0.1, 0.2, 0.9])
+    np.testing.assert_allclose(oracle.riemann_flux(L, R, 0, g, rs), _phys_flux_x(L, g), rtol=1e-13, atol=1e-14)
+    # Directions: the y flux of a state equals the x flux of the cyclically rotated state.
+    Wy = np.array([1.3, 0.7, 0.4, -0.2, 2.1])  # (rho, u, v, w, p) with v normal
+    Fy = oracle.riemann_flux(Wy, Wy, 1, g, rs)
+    Fx = _phys_flux_x(np.array([1.3, 0.4, -0.2, 0.7, 2.1]), g)  # frame (v, w, u)
+    np.testing.assert_allclose(Fy[[0, 2, 3, 1, 4]], Fx, rtol=1e-13, atol=1e-14)
+
+
+@pytest.mark.parametrize("rs", [0, 1, 3])
+def test_stationary_contact_is_exact(oracle, rs):
+    F = oracle.riemann_flux([2.0, 0, 0.3, -0.1, 1.5], [0.5, 0, -0.2, 0.4, 1.5], 0, 1.4, rs)
+    np.testing.assert_allclose(F, [0, 1.5, 0, 0, 0], atol=1e-14)
+
+
+def test_hlle_smears_stationary_contact(oracle):
+    F = oracle.riemann_flux([2.0, 0, 0, 0, 1.5], [0.5, 0, 0, 0, 1.5], 0, 1.4, 2)
+    assert F[0] > 1e-3  # HLLE has no contact wave: mass diffuses (paper Sec. 2)
+
+
+def test_riemann_matches_exact_on_weak_jumps(oracle):
+    """For small jumps every approximate solver approaches the exact flux (error O(jump^2))."""
+    g = 1.4
+    base = np.array([1.0, 0.2, 0.1, -0.1, 1.0])
+    for eps in (1e-2, 1e-3):
+        L = base * (1 + eps * np.array([1, 0.5, -0.3, 0.2, 0.8]))
+        R = base * (1 - eps * np.array([0.5, 1, 0.2, -0.4, 0.3]))
+        Fe = oracle.riemann_flux(L, R, 0, g, 3)
+        for rs in (0, 1):
+            assert np.max(np.abs(oracle.riemann_flux(L, R, 0, g, rs) - Fe)) < 3 * eps ** 2
+
+
+# ---------------------------------------------------------------------------
+# P12 / P13: Roe failure and HLLE positivity (paper Sec. 2)
+# ---------------------------------------------------------------------------
+def test_roe_fails_on_strong_double_rarefaction(oracle):
+    L, R = [1.0, -2.0, 0, 0, 0.4], [1.0, 2.0, 0, 0, 0.4]
+    assert not oracle.roe_ok(L, R, 1.4)
+    assert oracle.roe_ok([1.0, 0, 0, 0, 1.0], [0.125, 0, 0, 0, 0.1], 1.4)
+    # The fallback flux is the HLLE (default) or HLLC flux.
+    np.testing.assert_array_equal(oracle.riemann_flux(L, R, 0, 1.4, 0), oracle.riemann_flux(L, R, 0, 1.4, 2))
+    np.testing.assert_array_equal(oracle.riemann_flux(L, R, 0, 1.4, 0, 0x10),
+                                  oracle.riemann_flux(L, R, 0, 1.4, 1))
+
+
+def test_hlle_first_order_update_is_positive(oracle):
+    g = 1.4
+    n = 64
+    rho = np.ones(n)
+    u = np.where(np.arange(n) < n // 2, -2.0, 2.0)
+    p = np.full(n, 0.4)
+    c = np.sqrt(g * p / rho)
+    dtdh = 0.5 / np.max(np.abs(u) + c)
+    Wc = np.stack([rho, u, 0 * u, 0 * u, p], 1)
+    U = np.stack([rho, rho * u, 0 * u, 0 * u, p / (g - 1) + 0.5 * rho * u * u], 1)
+    for _ in range(40):
+        F = np.array([oracle.riemann_flux(Wc[i], Wc[(i + 1) % n], 0, g, 2) for i in range(n)])
+        U = U - dtdh * (F - np.roll(F, 1, axis=0))
+        r = U[:, 0]
+        pr = (g - 1) * (U[:, 4] - 0.5 * U[:, 1] ** 2 / r)
+        assert r.min() > 0 and pr.min() > 0
+        Wc = np.stack([r, U[:, 1] / r, 0 * r, 0 * r, pr], 1)
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_schemes_positive_and_fallback_counted_on_double_rarefaction(oracle, scheme):
+    g = 1.4
+    n = 32
+    x = (np.arange(n) + 0.5) / n
+    u = np.where(x < 0.5, -2.0, 2.0) * np.ones((1, 1, n))
+    U = W.primitive_to_conserved(np.ones((1, 1, n)), u, 0 * u, 0 * u, np.full((1, 1, n), 0.4), g)
+    dh = 1.0 / n
+    oracle.reset_stats()
+    V = U
+    for _ in range(5):
+        V = oracle.step_box(V, 0.3 * dh / 2.75, dh, g, scheme, 0, 0, 1, 0)
+        r = V[0]
+        pr = (g - 1) * (V[4] - 0.5 * (V[1] ** 2 + V[2] ** 2 + V[3] ** 2) / r)
+        assert r.min() > 0 and pr.min() > 0
+    assert oracle.stats()["roe_fail"] > 0
+
+
+# ---------------------------------------------------------------------------
+# P9 / P10 / P11: limiters, PPM edges, characteristic decomposition
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("lim", LIMITERS)
+def test_limiter_identities(oracle, lim):
+    for d in (0.37, -1.2e-3, 5.0):
+        assert abs(oracle.limiter(d, d, lim) - d) <= 2e-16 * abs(d)  # linear data: exact slope
+    for a, b in ((1.0, -2.0), (0.0, 3.0), (-0.5, 0.0), (2.0, -1e-9)):
+        assert oracle.limiter(a, b, lim) == 0.0  # extremum: zero slope
+    rng = np.random.default_rng(7)
+    for _ in range(200):
+        a, b = rng.standard_normal(2)
+        if a * b <= 0:
+            continue
+        s = oracle.limiter(a, b, lim)
+        # TVD region: same sign, between 0 and 2 min(|a|,|b|); symmetric; homogeneous.
+        assert s * a > 0 and abs(s) <= 2 * min(abs(a), abs(b)) + 1e-15
+        assert abs(s - oracle.limiter(b, a, lim)) <= 1e-15 * abs(s)
+        assert abs(oracle.limiter(3 * a, 3 * b, lim) - 3 * s) <= 1e-14 * abs(s)
+
+
+def test_limiter_textbook_values(oracle):
+    # r = dR/dL = 3 with dL = 1: van Leer phi = 2r/(1+r) = 1.5, van Albada phi = r(1+r)/(1+r^2) = 1.2,
+    # generalized minmod (theta 1.5) = min(1.5, 4.5, 2) = 1.5; hybrid = min of the two = 1.5.
+    assert abs(oracle.limiter(1.0, 3.0, 1) - 1.5) < 1e-15
+    assert abs(oracle.limiter(1.0, 3.0, 2) - 1.2) < 1e-15
+    assert abs(oracle.limiter(1.0, 3.0, 0) - 1.5) < 1e-15
+    assert abs(oracle.limiter(1.0, 3.0, 3) - 1.5) < 1e-15
+    # r = 1.2: central 1.1, van Leer 2*1.2/2.2, gen. minmod min(1.5,1.8,1.1) = 1.1, hybrid = min(1.1, 1.0909)
+    assert abs(oracle.limiter(1.0, 1.2, 0) - 1.1) < 1e-15
+    assert abs(oracle.limiter(1.0, 1.2, 3) - 2.4 / 2.2) < 1e-15
+
+
+def test_ppm_edge_exact_for_cubic_averages(oracle):
+    """With centred (unlimited) slopes the PPM edge is exact for cubics."""
+    P = np.polynomial.Polynomial([0.3, -1.1, 0.7, 0.25])
+    Q = P.integ()
+    h = 0.1
+    xs = np.arange(-2, 3) * h
+    avg = np.array([(Q(x + h / 2) - Q(x - h / 2)) / h for x in xs])  # cells -2..2
+    s = [0.5 * (avg[i + 1] - avg[i - 1]) for i in (1, 2, 3)]  # slopes of cells -1, 0, 1
+    wa, wb = np.full(5, avg[2]), np.full(5, avg[3])  # cells 0 and 1
+    e = oracle.ppm_edge(wa, wb, np.full(5, s[1]), np.full(5, s[2]))
+    assert np.allclose(e, P(0.5 * h), rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("flags", [0, CHAR])
+def test_slope_of_linear_profile_is_exact(oracle, flags):
+    w0 = np.array([1.0, 0.3, -0.2, 0.1, 2.0])
+    dw = np.array([0.01, -0.02, 0.005, 0.003, 0.04])
+    for d in (0, 1, 2):
+        for lim in LIMITERS:
+            s = oracle.slope(w0 - dw, w0, w0 + dw, d, 1.4, lim, flags)
+            np.testing.assert_allclose(s, dw, rtol=1e-12, atol=1e-17)
+
+
+def test_characteristic_roundtrip(oracle):
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        w = np.array([rng.uniform(0.1, 3), *rng.standard_normal(3), rng.uniform(0.1, 3)])
+        dw = rng.standard_normal(5)
+        a, back = oracle.char_roundtrip(w, dw, 5.0 / 3.0)
+        np.testing.assert_allclose(back, dw, rtol=1e-12, atol=1e-13)
+        # An entropy jump (density only) is a pure entropy wave.
+        a2, _ = oracle.char_roundtrip(w, [1.0, 0, 0, 0, 0], 5.0 / 3.0)
+        np.testing.assert_allclose(a2, [0, 1, 0, 0, 0], atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Riemann-solve counts (paper Sec. 3.2: MHM 3 per cell, VL and CTU 6)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("scheme,per_cell", [(0, 3), (1, 6), (2, 6)])
+def test_riemann_solves_per_cell(oracle, scheme, per_cell):
+    U = _random_smooth_box(8, 1.4, 1)
+    oracle.reset_stats()
+    oracle.step_box(U, 1e-3, 1 / 8, 1.4, scheme, 1, 1, 1, CHAR)
+    assert oracle.stats()["solves"] == per_cell * 8 ** 3
+
+
+# ---------------------------------------------------------------------------
+# P2 conservation, P3 free stream, P4 contact, P5 1D reduction
+# ---------------------------------------------------------------------------
+ALL_COMBOS = list(itertools.product(SCHEMES, RECONS, SOLVERS, (0, CHAR)))
+
+
+@pytest.mark.parametrize("scheme,recon,rs,flags", ALL_COMBOS)
+def test_conservation_periodic(oracle, scheme, recon, rs, flags):
+    g = 1.4
+    U = _random_smooth_box(8, g, 11, amp=0.3)
+    V = U
+    for _ in range(10):
+        V = oracle.step_box(V, 0.004, 1 / 8, g, scheme, recon, rs, 1, flags)
+    s0, s1 = U.reshape(5, -1).sum(1), V.reshape(5, -1).sum(1)
+    scale = np.abs(U).reshape(5, -1).sum(1)
+    assert np.all(np.abs(s1 - s0) <= 1e-13 * scale)
+
+
+@pytest.mark.parametrize("scheme,recon,rs,flags", ALL_COMBOS)
+def test_free_stream_is_bitwise_preserved(oracle, scheme, recon, rs, flags):
+    g = 1.4
+    one = np.ones((6, 5, 7))
+    U = W.primitive_to_conserved(1.7 * one, 0.3 * one, -0.8 * one, 0.45 * one, 2.2 * one, g)
+    V = oracle.step_box(U, 0.01, 0.1, g, scheme, recon, rs, 1, flags)
+    np.testing.assert_array_equal(V, U)
+
+
+@pytest.mark.parametrize("scheme,recon,rs,flags", ALL_COMBOS)
+def test_moving_contact_keeps_u_and_p(oracle, scheme, recon, rs, flags):
+    g = 1.4
+    n = 8
+    rng = np.random.default_rng(5)
+    rho = 1.0 + 0.5 * rng.uniform(size=(n, n, n))
+    one = np.ones_like(rho)
+    U = W.primitive_to_conserved(rho, 0.4 * one, -0.3 * one, 0.2 * one, 1.3 * one, g)
+    V = oracle.step_box(U, 0.01, 1 / n, g, scheme, recon, rs, 1, flags)
+    r = V[0]
+    np.testing.assert_allclose(V[1] / r, 0.4, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(V[2] / r, -0.3, rtol=0, atol=1e-13)
+    pr = (g - 1) * (V[4] - 0.5 * (V[1] ** 2 + V[2] ** 2 + V[3] ** 2) / r)
+    np.testing.assert_allclose(pr, 1.3, rtol=1e-13)
+
+
+@pytest.mark.parametrize("scheme,recon", list(itertools.product(SCHEMES, RECONS)))
+def test_one_dimensional_reduction(oracle, scheme, recon):
+    """Data uniform in y and z: the 3D step equals the 1D step in every row."""
+    g = 1.4
+    U1 = W.sod_box(32, gamma=g, noise=0.0, ny=1, nz=1)
+    U3 = np.broadcast_to(U1, (5, 4, 3, 32)).copy()
+    for flags in (0, CHAR):
+        a = oracle.step_box(U1, 0.01, 1 / 32, g, scheme, recon, 1, 1, flags)
+        b = oracle.step_box(U3, 0.01, 1 / 32, g, scheme, recon, 1, 1, flags)
+        np.testing.assert_array_equal(b, np.broadcast_to(a, b.shape))
+
+
+# ---------------------------------------------------------------------------
+# P6: symmetry (paper Sec. 1)
+# ---------------------------------------------------------------------------
+def _mirror_x(U):
+    V = U[:, :, :, ::-1].copy()
+    V[1] = -V[1]
+    return V
+
+
+def _cycle_axes(U):
+    """(x, y, z) -> (y, z, x): new field at (x', y', z') = (y, z, x) of the old."""
+    # old array [v][z][y][x]; new coordinates x'=y, y'=z, z'=x -> new[v][z'=x][y'=z][x'=y]
+    V = np.stack([np.transpose(U[v], (2, 0, 1)) for v in range(5)])
+    # momentum components follow: new (mx', my', mz') = (my, mz, mx)
+    V[1], V[2], V[3] = V[2].copy(), V[3].copy(), V[1].copy()
+    return V
+
+
+@pytest.mark.parametrize("scheme,recon,rs", list(itertools.product(SCHEMES, RECONS, SOLVERS)))
+def test_mirror_and_rotation_symmetry(oracle, scheme, recon, rs):
+    g = 1.4
+    U = _random_smooth_box(8, g, 21, amp=0.4)
+    for flags in (0, CHAR):
+        step = lambda X: oracle.step_box(X, 0.01, 1 / 8, g, scheme, recon, rs, 1, flags)
+        a = step(_mirror_x(U))
+        b = _mirror_x(step(U))
+        assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(U))
+        a = step(_cycle_axes(U))
+        b = _cycle_axes(step(U))
+        assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(U))
+
+
+def test_cycle_axes_is_a_rotation():
+    U = np.random.default_rng(0).standard_normal((5, 3, 4, 5))
+    V = _cycle_axes(_cycle_axes(_cycle_axes(U)))
+    np.testing.assert_array_equal(U, V)
+
+
+# ---------------------------------------------------------------------------
+# P16: whole periodic box == patch-group decomposition with ghosts
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("scheme,recon", list(itertools.product(SCHEMES, RECONS)))
+def test_box_equals_group_decomposition(oracle, scheme, recon):
+    g = 1.4
+    box = W.lognormal_blast_box(32, gamma=g, seed=4, radius_cells=3)
+    gw = oracle.ghost_width(scheme, recon)
+    G = oracle.fill_ghosts_periodic(box, gw)
+    for rs, flags in ((1, CHAR), (0, 0)):
+        out, flux = oracle.solve_groups(G, gw, 2e-3, 1 / 32, g, scheme, recon, rs, 1, flags | 0x04,
+                                        want_flux=True)
+        ref = oracle.step_box(box, 2e-3, 1 / 32, g, scheme, recon, rs, 1, flags)
+        np.testing.assert_array_equal(W.groups_to_box(out, 32, 32, 32), ref)
+        # Fluxes across shared faces of neighbouring groups agree bitwise.
+        # group (gx=0,gy=0,gz=0) + face and group (gx=1) - face:
+        np.testing.assert_array_equal(flux[0, 0, 1], flux[1, 0, 0])
+        # y faces: group 0 + face == group 2 (gy=1) - face; z: group 0 + == group 4 -
+        np.testing.assert_array_equal(flux[0, 1, 1], flux[2, 1, 0])
+        np.testing.assert_array_equal(flux[0, 2, 1], flux[4, 2, 0])
+        # Conservation through the stored fluxes: group update == sum of face fluxes (mass).
+        dtdh = 2e-3 * 32
+        Gi = G[:, :, gw:gw + 16, gw:gw + 16, gw:gw + 16]
+        dm = (out[:, 0] - Gi[:, 0]).sum(axis=(1, 2, 3))
+        ff = flux[:, :, 1, 0].sum(axis=(2, 3)) - flux[:, :, 0, 0].sum(axis=(2, 3))
+        np.testing.assert_allclose(dm, -dtdh * ff.sum(1), atol=1e-11)
+
+
+def test_ghost_widths(oracle):
+    assert [oracle.ghost_width(s, r) for s in SCHEMES for r in RECONS] == [2, 3, 3, 4, 2, 3]
+
+
+def test_group_mode_rejects_thin_ghosts(oracle):
+    G = np.ones((1, 5, 20, 20, 20))
+    with pytest.raises(ValueError):
+        oracle.solve_groups(G, 2, 1e-3, 1.0, 1.4, 1, 1, 1, 1)  # VL+PPM needs 4
+
+
+# ---------------------------------------------------------------------------
+# P7: second-order convergence on smooth linear waves
+# ---------------------------------------------------------------------------
+def _wave_error(oracle, scheme, recon, n, kvec, dims, cfl=0.4, gamma=5.0 / 3.0):
+    U0, T = W.sound_wave_box(*dims(n), gamma=gamma, amp=1e-6, kvec=kvec)
+    dh = 1.0 / n
+    nst = int(np.ceil(T / (cfl * dh)))
+    U = U0
+    for _ in range(nst):
+        U = oracle.step_box(U, T / nst, dh, gamma, scheme, recon, 1, 1, 0)
+    return np.abs(U[0] - U0[0]).mean()
+
+
+@pytest.mark.parametrize("scheme,recon,min_order", [(0, 0, 1.9), (1, 0, 1.9), (2, 0, 1.9), (2, 1, 1.9),
+                                                    (0, 1, 1.5), (1, 1, 1.4)])
+def test_convergence_1d(oracle, scheme, recon, min_order):
+    e = [_wave_error(oracle, scheme, recon, n, (1, 0, 0), lambda n: (n, 1, 1)) for n in (64, 128, 256)]
+    orders = np.log2(np.array(e[:-1]) / np.array(e[1:]))
+    assert orders.min() >= min_order, (e, orders)
+
+
+@pytest.mark.parametrize("scheme,recon", [(0, 0), (1, 0), (2, 0), (2, 1)])
+def test_convergence_2d_oblique(oracle, scheme, recon):
+    e = [_wave_error(oracle, scheme, recon, n, (1, 1, 0), lambda n: (n, n, 1)) for n in (32, 64)]
+    assert np.log2(e[0] / e[1]) >= 1.85, e
+
+
+# ---------------------------------------------------------------------------
+# P1 on the schemes: Sod shock tube
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("scheme,recon,rs,flags", [c for c in ALL_COMBOS if c[2] != 2 or c[1] == 0])
+def test_sod_shock_position_and_plateau(oracle, scheme, recon, rs, flags):
+    g = 1.4
+    n = 128
+    U = W.sod_box(n, gamma=g, noise=0.0, ny=1, nz=1)
+    dh = 1.0 / n
+    t, tend = 0.0, 0.1
+    cfl = 0.8 if scheme == 2 else 0.6  # 1D: CFL limit is 1 for every scheme
+    while t < tend - 1e-14:
+        dt = min(oracle.cfl_dt(U, dh, g, cfl), tend - t)
+        U = oracle.step_box(U, dt, dh, g, scheme, recon, rs, 1, flags)
+        t += dt
+    x = (np.arange(n) + 0.5) / n
+    star, Wex = oracle.exact_riemann([1, 0, 0, 0, 1], [0.125, 0, 0, 0, 0.1], g, (x - 0.5) / tend)
+    rho = U[0, 0, 0]
+    # Shock position: where rho crosses the mid value between rho*_R and 0.125 (right half only).
+    mid = 0.5 * (star["rhoR"] + 0.125)
+    right = slice(int(0.55 * n), int(0.78 * n))  # excludes the mirrored shock near x = 0.825
+    xs_num = x[right][np.argmin(np.abs(rho[right] - mid))]
+    S = star["rhoR"] * star["u"] / (star["rhoR"] - 0.125)
+    assert abs(xs_num - (0.5 + S * tend)) <= 1.0 * dh + 1e-12
+    # Plateau pressure and velocity between the contact and the shock.
+    pr = (g - 1) * (U[4, 0, 0] - 0.5 * U[1, 0, 0] ** 2 / rho)
+    xc = 0.5 + star["u"] * tend
+    plateau = (x > xc + 4 * dh) & (x < 0.5 + S * tend - 4 * dh)
+    assert np.all(np.abs(pr[plateau] - star["p"]) < 0.01)
+    assert np.all(np.abs(U[1, 0, 0][plateau] / rho[plateau] - star["u"]) < 0.02)
+    # The periodic box holds a mirrored problem at x = 0 = 1; compare where only
+    # the middle problem's waves have arrived by t = 0.1.
+    inner = (x > 0.15) & (x < 0.8)
+    l1 = np.abs(rho - Wex[:, 0])[inner].mean()
+    assert l1 < 0.012, l1
+
+
+def test_sod_l1_decreases_with_resolution(oracle):
+    g = 1.4
+    errs = []
+    for n in (64, 128, 256):
+        U = W.sod_box(n, gamma=g, noise=0.0, ny=1, nz=1)
+        dh = 1.0 / n
+        t = 0.0
+        while t < 0.1 - 1e-14:
+            dt = min(oracle.cfl_dt(U, dh, g, 0.8), 0.1 - t)
+            U = oracle.step_box(U, dt, dh, g, 2, 1, 1, 1, CHAR)
+            t += dt
+        x = (np.arange(n) + 0.5) / n
+        _, Wex = oracle.exact_riemann([1, 0, 0, 0, 1], [0.125, 0, 0, 0, 0.1], g, (x - 0.5) / 0.1)
+        inner = (x > 0.15) & (x < 0.8)
+        errs.append(np.abs(U[0, 0, 0] - Wex[:, 0])[inner].mean())
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[0] / errs[2] > 2.5  # about first order at discontinuities
+
+
+def test_contact_diffusion_ordering(oracle):
+    """PPM resolves a moving contact more sharply than PLM; HLLE smears it
+    more than HLLC and Roe (paper Sec. 2)."""
+    g = 1.4
+    n = 64
+    x = (np.arange(n) + 0.5) / n
+    rho = np.where((x > 0.25) & (x < 0.75), 2.0, 1.0)[None, None, :]
+    one = np.ones_like(rho)
+    U0 = W.primitive_to_conserved(rho, one, 0 * one, 0 * one, one, g)
+
+    def err(scheme, recon, rs):
+        U = U0
+        for _ in range(4 * n):  # advect once around the box (u = 1, dt = dh / 4)
+            U = oracle.step_box(U, 0.25 / n, 1 / n, g, scheme, recon, rs, 1, 0)
+        return np.abs(U[0] - U0[0]).mean()
+
+    e = {(rec, rs): err(2, rec, rs) for rec in (0, 1) for rs in (0, 1, 2)}
+    for rs in (0, 1, 2):
+        assert e[(1, rs)] < e[(0, rs)]
+    for rec in (0, 1):
+        assert e[(rec, 2)] > e[(rec, 1)] and e[(rec, 2)] > e[(rec, 0)]
+
+
+def test_characteristic_limiting_reduces_oscillation(oracle):
+    """Characteristic interpolation reduces spurious oscillations in a shock
+    tube (paper Sec. 2): total variation of rho is not larger than with
+    primitive interpolation."""
+    g = 1.4
+    n = 128
+    tv = {}
+    for flags in (0, CHAR):
+        U = W.sod_box(n, gamma=g, noise=0.0, ny=1, nz=1)
+        t = 0.0
+        while t < 0.1 - 1e-14:
+            dt = min(oracle.cfl_dt(U, 1 / n, g, 0.8), 0.1 - t)
+            U = oracle.step_box(U, dt, 1 / n, g, 2, 1, 0, 1, flags)
+            t += dt
+        r = U[0, 0, 0]
+        tv[flags] = np.abs(np.diff(r[n // 4: 3 * n // 4])).sum()
+    assert tv[CHAR] <= tv[0] * (1 + 1e-9)
+
+
+# ---------------------------------------------------------------------------
+# P14: linear amplification of the (pi,pi,pi) acoustic checkerboard
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("scheme,factor", [(0, lambda nu: 1 - 6 * nu), (1, lambda nu: 1 - 6 * nu + 18 * nu * nu)])
+def test_checkerboard_amplification(oracle, scheme, factor):
+    g = 1.4
+    n = 8
+    idx = np.indices((n, n, n)).sum(0)
+    sgn = np.where(idx % 2 == 0, 1.0, -1.0)
+    eps = 1e-8
+    p0, r0 = 1.0, 1.0
+    c0 = np.sqrt(g * p0 / r0)
+    U = W.primitive_to_conserved(r0 + eps * sgn / c0 ** 2, 0 * sgn, 0 * sgn, 0 * sgn, p0 + eps * sgn, g)
+    dh = 1.0 / n
+    for nu in (0.1, 0.3, 0.5):
+        V = oracle.step_box(U, nu * dh / c0, dh, g, scheme, 0, 1, 1, 0)
+        pr = (g - 1) * (V[4] - 0.5 * (V[1] ** 2 + V[2] ** 2 + V[3] ** 2) / V[0])
+        ratio = (pr[0, 0, 0] - p0) / eps
+        assert abs(ratio - factor(nu)) < 1e-5, (nu, ratio, factor(nu))
+
+
+# ---------------------------------------------------------------------------
+# Time step, sums, ghost fill
+# ---------------------------------------------------------------------------
+def test_cfl_dt_and_sums(oracle):
+    g = 5.0 / 3.0
+    U = W.sod_box(32, gamma=g, noise=0.0)
+    dt = oracle.cfl_dt(U, 1 / 32, g, 0.5)
+    assert abs(dt - 0.5 / 32 / np.sqrt(g)) < 1e-16  # rest state: max signal speed = c_L = sqrt(gamma)
+    s = oracle.conserved_sums(U, 1 / 32)
+    np.testing.assert_allclose(s[0], 0.5 * 1.0 + 0.5 * 0.125, rtol=1e-12)
+    np.testing.assert_allclose(s[4], (0.5 * 1.0 + 0.5 * 0.1) / (g - 1), rtol=1e-12)
+    np.testing.assert_allclose(s[1:4], 0, atol=1e-16)
+
+
+def test_periodic_ghost_fill_wraps(oracle):
+    box = np.arange(5 * 32 * 16 * 16, dtype=np.float64).reshape(5, 16, 16, 32)
+    G = oracle.fill_ghosts_periodic(box, 2)
+    assert G.shape == (2, 5, 20, 20, 20)
+    np.testing.assert_array_equal(G[0, :, 2:18, 2:18, 2:18], box[:, :, :, :16])
+    np.testing.assert_array_equal(G[0, :, 2:18, 2:18, 0:2], box[:, :, :, 30:32])  # x wraps to the far end
+    np.testing.assert_array_equal(G[1, :, 2:18, 2:18, 0:2], box[:, :, :, 14:16])
+    np.testing.assert_array_equal(G[0, :, 0, 2:18, 2:18], box[:, 14, :, :16])  # z wraps (nz = 16)
