@@ -1,0 +1,193 @@
+/*
+ * hydro.h -- C ABI of the MI355X (gfx950) patch-group hydrodynamic solver.
+ *
+ * The library advances batches of patch groups -- 2x2x2 patches of 8^3
+ * cells, i.e. 16^3 interior cells plus a ghost layer -- of the 3D Euler
+ * equations by one step with the directionally unsplit schemes of
+ * Schive, Zhang & Chiueh, arXiv:1103.3373:
+ *   Sec. 2      : MUSCL-Hancock (MHM), the VL variant and the six-solve CTU
+ *                 scheme; PLM / PPM reconstruction with the generalized
+ *                 minmod, van Leer, van Albada or hybrid limiter, applied to
+ *                 primitive or characteristic variables; Roe (with detection
+ *                 of linearization failure and HLLE/HLLC fallback), HLLC and
+ *                 HLLE Riemann solvers; steps (1)-(5): reconstruction (plus
+ *                 characteristic tracing for CTU), Riemann solves, transverse
+ *                 correction (CTU), conservative update, patch-boundary
+ *                 fluxes.
+ *   Sec. 3.1    : one patch group per work unit, data array[z][y][x] with x
+ *                 fastest, fluxes across patch boundaries stored as soon as
+ *                 they are computed.
+ *   Sec. 4.1-4.2: inputs are the interior plus ghost cells of each group
+ *                 (the "preparation step"), outputs the updated interiors.
+ *   Sec. 4.3    : the evolution time step (CFL condition).
+ *
+ * Conventions for every entry point
+ *  - Pointers are DEVICE pointers unless marked (host).  The caller allocates
+ *    and owns every buffer; the library never frees caller memory.
+ *  - Buffers hold float, or double when flags contain HYDRO_F64.
+ *  - Conserved variables (rho, rho*u, rho*v, rho*w, E), ideal gas.
+ *  - Calls are asynchronous on `stream` (a hipStream_t; NULL = null stream).
+ *    Kernel faults surface at the caller's next synchronization.
+ *  - Return 0 on success or a negative HYDRO_E* code; hydro_last_error()
+ *    gives the message of the last failure on the calling thread.
+ *  - Numerical trouble is never an error: Roe fallbacks and floor
+ *    activations are counted on the device (hydro_get_diag).
+ */
+#ifndef HYDRO_H
+#define HYDRO_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Schemes (Sec. 2). */
+enum hydro_scheme { HYDRO_MHM = 0, HYDRO_VL = 1, HYDRO_CTU = 2 };
+/* Reconstruction (Sec. 2). */
+enum hydro_recon { HYDRO_PLM = 0, HYDRO_PPM = 1 };
+/* Riemann solvers (Sec. 2).  The exact solver is not built on the GPU. */
+enum hydro_riemann { HYDRO_ROE = 0, HYDRO_HLLC = 1, HYDRO_HLLE = 2 };
+/* Slope limiters (Sec. 2).  The hybrid limiter is the van Leer slope bounded
+ * by the generalized minmod slope; theta = 1.5 for both. */
+enum hydro_limiter { HYDRO_LIM_GMINMOD = 0, HYDRO_LIM_VANLEER = 1, HYDRO_LIM_VANALBADA = 2, HYDRO_LIM_HYBRID = 3 };
+
+/* flags */
+#define HYDRO_F64 0x01          /* buffers hold double (default float) */
+#define HYDRO_CHAR 0x02         /* limit characteristic variables (Sec. 2) */
+#define HYDRO_FLUX_MID 0x04     /* flux_out also holds the internal patch mid planes */
+#define HYDRO_PLAIN 0x08        /* plain per-group path (Sec. 3.1 design); default: fused path */
+#define HYDRO_ROE_FB_HLLC 0x10  /* Roe fallback flux = HLLC (default HLLE) */
+#define HYDRO_BOX_GROUPED 0x20  /* hydro_fill_ghosts_periodic: box is [G][5][16][16][16] */
+
+/* error codes */
+#define HYDRO_OK 0
+#define HYDRO_EINVAL (-1)       /* bad argument */
+#define HYDRO_EUNSUPPORTED (-2) /* combination not built */
+#define HYDRO_EHIP (-3)         /* HIP runtime error (message in hydro_last_error) */
+#define HYDRO_EALIAS (-4)       /* input and output buffers overlap */
+
+/*
+ * Ghost width g needed by a scheme's stencil: MHM and CTU: PLM 2, PPM 3;
+ * VL: PLM 3, PPM 4 (the first-order predictor adds one layer).  Group input
+ * arrays are (16 + 2g)^3 per variable.  Returns -1 for a bad enum.
+ */
+int hydro_ghost_width(int scheme, int reconstruction);
+
+/*
+ * Advance n_groups patch groups by one step of size dt (Sec. 2, steps 1-5).
+ *   in        [n_groups][5][N][N][N], N = 16 + 2*hydro_ghost_width(...): the
+ *             interior and ghost cells of each group (Sec. 4.2), x fastest.
+ *   out       [n_groups][5][16][16][16]: the updated interiors.  Must not
+ *             overlap `in` or `flux_out` (HYDRO_EALIAS).
+ *   flux_out  NULL, or [n_groups][3][nf][5][16][16]: the final physical flux
+ *             F (not F*dt) on the group's faces (Sec. 2 step 5), dir x,y,z;
+ *             face index 0 = lower face (interior offset 0), 1 = upper face
+ *             (offset 16), and with HYDRO_FLUX_MID nf = 3 and index 2 = the
+ *             internal patch boundary (offset 8); otherwise nf = 2.  The two
+ *             transverse indices are (slow, fast) = (z,y) for x faces, (z,x)
+ *             for y faces, (y,x) for z faces.
+ *   dt, dh    time step and cell size (host doubles, > 0, finite); dt/dh is
+ *             formed in double and rounded once for the float path.
+ *   gamma     ratio of specific heats, > 1.
+ * n_groups == 0 is a successful no-op.  Errors: HYDRO_EINVAL, HYDRO_EALIAS,
+ * HYDRO_EUNSUPPORTED, HYDRO_EHIP.
+ */
+int hydro_solve_groups(const void* in, void* out, void* flux_out, int n_groups, double dt, double dh, double gamma,
+                       int scheme, int reconstruction, int riemann, int limiter, int flags, void* stream);
+
+/*
+ * CFL time step (Sec. 4.3) in FP64 from interior cells U[n_groups][5][4096]:
+ *   dt = cfl * dh / max over cells of max_d(|v_d| + c).
+ * Written to dt_out (device, 1 double).  The maximum is order-free, so the
+ * result equals a serial FP64 evaluation on the same (upcast) data.
+ */
+int hydro_cfl_dt(const void* U, int n_groups, double dh, double gamma, double cfl, int flags, double* dt_out,
+                 void* stream);
+
+/*
+ * FP64 conserved sums over interior cells U[n_groups][5][4096]:
+ *   sums_out[v] = dh^3 * sum U_v  (device, 5 doubles), fixed reduction order.
+ */
+int hydro_conserved_sums(const void* U, int n_groups, double dh, int flags, double* sums_out, void* stream);
+
+/*
+ * Preparation step (Sec. 4.2), periodic box: build the ghosted groups
+ * [G][5][N][N][N] (N = 16 + 2g, G = (gz*ngy + gy)*ngx + gx) from a box
+ * [5][nz][ny][nx] (or [G][5][16][16][16] with HYDRO_BOX_GROUPED).  nx, ny,
+ * nz must be positive multiples of 16; 0 <= g <= 16.
+ */
+int hydro_fill_ghosts_periodic(const void* box, int nx, int ny, int nz, int g, int flags, void* groups_out,
+                               void* stream);
+
+/*
+ * Preparation step (Sec. 4.2) for AMR-shaped groups: every cell of each
+ * padded group is the trilinear interpolation, at the cell centre, of a
+ * periodic coarse field coarse[5][cn][cn][cn] on the unit box (spatial
+ * interpolation at coarse-fine boundaries).  layout (device int32
+ * [n_groups][4]) = (level, ox, oy, oz): the group's first interior cell on
+ * the level grid of spacing base_dh / 2^level.
+ */
+int hydro_fill_groups_interp(const void* coarse, int cn, const int* layout, int n_groups, int g, double base_dh,
+                             int flags, void* groups_out, void* stream);
+
+/* One segment of a batched launch: groups in[count][5][N^3] -> out, flux,
+ * advanced by dt = (*dt) * dt_scale with cell size dh.  `dt` points to a
+ * device double, so the time step can be produced on the device (e.g. by
+ * hydro_cfl_dt) and the launch captured in a graph. */
+struct hydro_seg {
+  const void* in;
+  void* out;
+  void* flux;          /* may be NULL */
+  const double* dt;    /* device */
+  double dt_scale;
+  double dh;
+  long long first;     /* global index of the segment's first group */
+  long long count;     /* groups in the segment */
+};
+
+/* Specialization of a batched launch (all segments share it). */
+struct hydro_spec {
+  int scheme, reconstruction, riemann, limiter, flags;
+  double gamma;
+};
+
+/*
+ * Batched solve (uneven levels / simulations in one launch): one persistent
+ * launch of the fused kernel over segs[0..n_segs) (device table, segments in
+ * increasing `first`, covering [0, n_groups_total)).  The launch shape comes
+ * from the autotune cache (hydro_autotune) or a default.  Same layouts and
+ * errors as hydro_solve_groups; HYDRO_PLAIN is not accepted here.
+ */
+int hydro_solve_batch(const struct hydro_seg* segs, int n_segs, long long n_groups_total,
+                      const struct hydro_spec* spec, void* stream);
+
+/*
+ * Autotuner: times the fused kernel's launch shapes for `spec` on a
+ * synthetic batch of n_groups_hint groups (allocates and frees its own
+ * buffers; synchronizes `stream`) and records the fastest in the in-process
+ * cache used by hydro_solve_groups / hydro_solve_batch.  If the environment
+ * variable HYDRO_TUNE_CACHE names a file, the cache is appended there and
+ * read back at the first call.  Returns the chosen workgroup count (> 0).
+ */
+int hydro_autotune(const struct hydro_spec* spec, int n_groups_hint, void* stream);
+
+/* Device diagnostics accumulated since the last reset. */
+struct hydro_diag {
+  unsigned long long roe_fallbacks; /* interfaces where Roe's linearization failed */
+  unsigned long long floor_hits;    /* density/pressure floor activations */
+};
+/* Synchronizes `stream`, copies the counters to *out (host); reset != 0
+ * clears them afterwards. */
+int hydro_get_diag(struct hydro_diag* out, int reset, void* stream);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* hydro_last_error(void);
+
+/* Frees the library's internal workspaces (plain-path temporaries,
+ * reduction partials, tuning state).  Synchronizes the device. */
+void hydro_shutdown(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HYDRO_H */

@@ -57,6 +57,8 @@ def _lib(counting: bool = False) -> ctypes.CDLL:
     L.oracle_solve_groups.restype = i
     L.oracle_fill_ghosts_periodic.argtypes = [P, i, i, i, i, P]
     L.oracle_fill_ghosts_periodic.restype = i
+    L.oracle_fill_groups_interp.argtypes = [P, i, P, i, i, d, P]
+    L.oracle_fill_groups_interp.restype = i
     L.oracle_cfl_dt.argtypes = [P, ctypes.c_long, ctypes.c_long, d, d, d]
     L.oracle_cfl_dt.restype = d
     L.oracle_conserved_sums.argtypes = [P, ctypes.c_long, ctypes.c_long, d, P]
@@ -142,6 +144,18 @@ def fill_ghosts_periodic(box, g) -> np.ndarray:
     rc = _lib().oracle_fill_ghosts_periodic(_p(box), nx, ny, nz, g, _p(out))
     if rc != 0:
         raise ValueError("oracle_fill_ghosts_periodic failed")
+    return out
+
+
+def fill_groups_interp(coarse, layout, g, base_dh) -> np.ndarray:
+    """Trilinear groups [n][5][N]^3 from a periodic coarse field [5][cn]^3;
+    layout int32 [n][4] = (level, ox, oy, oz)."""
+    coarse = _f64(coarse)
+    layout = np.ascontiguousarray(layout, dtype=np.int32)
+    n = layout.shape[0]
+    N = 16 + 2 * g
+    out = np.empty((n, 5, N, N, N))
+    _lib().oracle_fill_groups_interp(_p(coarse), coarse.shape[1], _p(layout), n, g, base_dh, _p(out))
     return out
 
 

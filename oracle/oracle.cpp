@@ -923,6 +923,51 @@ int oracle_fill_ghosts_periodic(const double* box, int nx, int ny, int nz, int g
   return 0;
 }
 
+// AMR-shaped groups: each padded-group cell is the trilinear interpolation,
+// at its centre, of a periodic coarse field [5][cn][cn][cn] on the unit box
+// (spatial interpolation at coarse-fine boundaries, Sec. 4.2).  layout[G] =
+// (level, ox, oy, oz), the first interior cell on the level grid with
+// spacing base_dh / 2^level.
+int oracle_fill_groups_interp(const double* coarse, int cn, const int* layout, int n_groups, int g, double base_dh,
+                              double* groups) {
+  int N = 16 + 2 * g;
+  long gc = (long)N * N * N, cc = (long)cn * cn * cn;
+  for (int G = 0; G < n_groups; ++G) {
+    const int* L = layout + 4 * G;
+    double dh = base_dh / (double)(1 << L[0]);
+    for (int k = 0; k < N; ++k)
+      for (int j = 0; j < N; ++j)
+        for (int i = 0; i < N; ++i) {
+          // position of the cell centre in units of coarse cells, relative to coarse centres
+          double pos[3] = {((double)(L[1] + i - g) + 0.5) * dh * cn - 0.5,
+                           ((double)(L[2] + j - g) + 0.5) * dh * cn - 0.5,
+                           ((double)(L[3] + k - g) + 0.5) * dh * cn - 0.5};
+          int lo[3], hi[3];
+          double w[3];
+          for (int a = 0; a < 3; ++a) {
+            double f = std::floor(pos[a]);
+            w[a] = pos[a] - f;
+            int l = (int)f;
+            lo[a] = ((l % cn) + cn) % cn;
+            hi[a] = (lo[a] + 1) % cn;
+          }
+          for (int n = 0; n < 5; ++n) {
+            const double* c = coarse + n * cc;
+            double v = 0.0;
+            for (int dz = 0; dz < 2; ++dz)
+              for (int dy = 0; dy < 2; ++dy)
+                for (int dx = 0; dx < 2; ++dx) {
+                  double wt = (dx ? w[0] : 1.0 - w[0]) * (dy ? w[1] : 1.0 - w[1]) * (dz ? w[2] : 1.0 - w[2]);
+                  long q = ((long)(dz ? hi[2] : lo[2]) * cn + (dy ? hi[1] : lo[1])) * cn + (dx ? hi[0] : lo[0]);
+                  v += wt * c[q];
+                }
+            groups[(long)G * 5 * gc + n * gc + ((long)k * N + j) * N + i] = v;
+          }
+        }
+  }
+  return 0;
+}
+
 // CFL time step from conserved cells (any layout; n_cells cells per
 // variable-plane, n_blocks blocks of [5][n_cells]):
 //   dt = cfl * dh / max over cells of max_d(|v_d| + c).

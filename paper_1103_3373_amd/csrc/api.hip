@@ -1,0 +1,513 @@
+// Host side of the C ABI declared in include/hydro.h: argument validation,
+// dispatch to the plain or fused kernels, library-owned workspaces, device
+// diagnostics and the launch-shape autotuner.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "hydro.h"
+#include "hydro_internal.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+int hip_fail(hipError_t e, const char* what) {
+  return fail(HYDRO_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+const int kKnownFlags = HYDRO_F64 | HYDRO_CHAR | HYDRO_FLUX_MID | HYDRO_PLAIN | HYDRO_ROE_FB_HLLC | HYDRO_BOX_GROUPED;
+
+int ghost_width(int scheme, int recon) {
+  if (scheme < 0 || scheme > 2 || recon < 0 || recon > 1) return -1;
+  int r = recon == HYDRO_PPM ? 2 : 1;
+  return scheme == HYDRO_VL ? r + 2 : r + 1;
+}
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  if (!a || !b || na == 0 || nb == 0) return false;
+  const char* x = (const char*)a;
+  const char* y = (const char*)b;
+  return x < y + nb && y < x + na;
+}
+
+// Library-owned device memory, one set per (device, stream).
+struct Workspace {
+  void* plain = nullptr;
+  size_t plain_bytes = 0;
+  double* partial = nullptr;  // reduction partials
+};
+struct DeviceState {
+  unsigned long long* diag = nullptr;
+  std::map<hipStream_t, Workspace> ws;
+};
+std::mutex g_mu;
+std::map<int, DeviceState> g_dev;
+
+const int kPartials = 1024;   // reduction partials (fixed: deterministic order)
+const int kPlainGridMax = 512; // plain path: workgroups (each owns 50 N^3 temporaries)
+
+int current_device(int* dev) {
+  hipError_t e = hipGetDevice(dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  return 0;
+}
+
+// Returns the device state (creating the diagnostics counters on first use).
+int device_state(DeviceState** out) {
+  int dev;
+  if (int rc = current_device(&dev)) return rc;
+  DeviceState& d = g_dev[dev];
+  if (!d.diag) {
+    hipError_t e = hipMalloc((void**)&d.diag, 2 * sizeof(unsigned long long));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(diag)");
+    e = hipMemset(d.diag, 0, 2 * sizeof(unsigned long long));
+    if (e != hipSuccess) return hip_fail(e, "hipMemset(diag)");
+  }
+  *out = &d;
+  return 0;
+}
+
+int ensure_plain(Workspace& w, size_t bytes) {
+  if (w.plain_bytes >= bytes) return 0;
+  if (w.plain) {
+    hipDeviceSynchronize();
+    hipFree(w.plain);
+    w.plain = nullptr;
+    w.plain_bytes = 0;
+  }
+  hipError_t e = hipMalloc(&w.plain, bytes);
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc(plain workspace)");
+  w.plain_bytes = bytes;
+  return 0;
+}
+int ensure_partial(Workspace& w) {
+  if (w.partial) return 0;
+  hipError_t e = hipMalloc((void**)&w.partial, (size_t)kPartials * 5 * sizeof(double));
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc(partials)");
+  return 0;
+}
+template <typename T>
+hy::Phys<T> make_phys(double dt, double dh, double gamma, int limiter, int flags) {
+  hy::Phys<T> p;
+  p.gamma = (T)gamma;
+  p.gm1 = (T)(gamma - 1.0);
+  p.inv_gm1 = (T)(1.0 / (gamma - 1.0));
+  p.dtdh = (T)(dt / dh);
+  p.hdtdh = (T)(0.5 * dt / dh);
+  p.theta = (T)1.5;
+  p.floor = (T)1e-10;
+  p.limiter = limiter;
+  p.charlim = (flags & HYDRO_CHAR) ? 1 : 0;
+  p.roe_fb_hllc = (flags & HYDRO_ROE_FB_HLLC) ? 1 : 0;
+  return p;
+}
+
+int check_options(int scheme, int recon, int riemann, int limiter, int flags) {
+  if (ghost_width(scheme, recon) < 0) return fail(HYDRO_EINVAL, "bad scheme %d or reconstruction %d", scheme, recon);
+  if (riemann == 3) return fail(HYDRO_EUNSUPPORTED, "the exact Riemann solver is not built on the GPU");
+  if (riemann < 0 || riemann > 2) return fail(HYDRO_EINVAL, "bad riemann %d", riemann);
+  if (limiter < 0 || limiter > 3) return fail(HYDRO_EINVAL, "bad limiter %d", limiter);
+  if (flags & ~kKnownFlags) return fail(HYDRO_EINVAL, "unknown flag bits 0x%x", flags & ~kKnownFlags);
+  return 0;
+}
+
+// ---- launch-shape cache (autotuner) ----------------------------------------
+std::map<std::string, int> g_tune;
+bool g_tune_loaded = false;
+
+std::string tune_key(int f64, int scheme, int recon, int riemann, int charlim) {
+  char b[96];
+  snprintf(b, sizeof(b), "gfx950/%s/s%d/r%d/rs%d/c%d", f64 ? "f64" : "f32", scheme, recon, riemann, charlim);
+  return b;
+}
+void tune_load() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = getenv("HYDRO_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = fopen(path, "r");
+  if (!f) return;
+  char key[128];
+  int v;
+  while (fscanf(f, "%127s %d", key, &v) == 2) g_tune[key] = v;
+  fclose(f);
+}
+int default_grid(long long n_groups) {
+  // Persistent launch: a fixed multiple of the CU count, never more than the
+  // number of groups.
+  int cus = 256;
+  hipDeviceProp_t prop;
+  int dev;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    cus = prop.multiProcessorCount;
+  long long g = (long long)cus * 4;
+  if (g > n_groups) g = n_groups;
+  return (int)(g < 1 ? 1 : g);
+}
+int tuned_grid(int f64, int scheme, int recon, int riemann, int charlim, long long n_groups) {
+  tune_load();
+  auto it = g_tune.find(tune_key(f64, scheme, recon, riemann, charlim));
+  int g = (it != g_tune.end()) ? it->second : default_grid(n_groups);
+  if (g > n_groups) g = (int)n_groups;
+  return g < 1 ? 1 : g;
+}
+
+template <typename T>
+int run_fused(const hy::Seg* segs_dev, int n_segs, long long n_groups, int g, int scheme, int recon, int riemann,
+              int limiter, int flags, double gamma, unsigned long long* diag, int grid, hipStream_t st,
+              const hy::Seg* seg0 = nullptr, double dt0 = 0.0) {
+  hy::FusedArgs<T> a;
+  a.segs = segs_dev;
+  a.n_segs = n_segs;
+  a.n_groups = n_groups;
+  a.g = g;
+  a.nf = (flags & HYDRO_FLUX_MID) ? 3 : 2;
+  a.gamma = (T)gamma;
+  a.theta = (T)1.5;
+  a.floor = (T)1e-10;
+  a.limiter = limiter;
+  a.charlim = (flags & HYDRO_CHAR) ? 1 : 0;
+  a.roe_fb_hllc = (flags & HYDRO_ROE_FB_HLLC) ? 1 : 0;
+  a.diag = diag;
+  if (seg0) a.seg0 = *seg0;
+  else memset(&a.seg0, 0, sizeof(a.seg0));
+  a.dt0 = dt0;
+  hy::FusedCfg cfg;
+  cfg.grid = grid;
+  hipError_t e = hy::launch_fused(a, scheme, recon, riemann, cfg, st);
+  if (e != hipSuccess) return hip_fail(e, "fused solver launch");
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hydro_ghost_width(int scheme, int reconstruction) { return ghost_width(scheme, reconstruction); }
+
+const char* hydro_last_error(void) { return g_err; }
+
+int hydro_solve_groups(const void* in, void* out, void* flux_out, int n_groups, double dt, double dh, double gamma,
+                       int scheme, int reconstruction, int riemann, int limiter, int flags, void* stream) {
+  g_err[0] = 0;
+  if (int rc = check_options(scheme, reconstruction, riemann, limiter, flags)) return rc;
+  if (n_groups < 0) return fail(HYDRO_EINVAL, "n_groups %d < 0", n_groups);
+  if (!(dt > 0.0) || !isfinite(dt)) return fail(HYDRO_EINVAL, "dt must be positive and finite");
+  if (!(dh > 0.0) || !isfinite(dh)) return fail(HYDRO_EINVAL, "dh must be positive and finite");
+  if (!(gamma > 1.0) || !isfinite(gamma)) return fail(HYDRO_EINVAL, "gamma must exceed 1");
+  if (n_groups == 0) return 0;
+  if (!in || !out) return fail(HYDRO_EINVAL, "null in/out with n_groups > 0");
+  const int g = ghost_width(scheme, reconstruction);
+  const int N = 16 + 2 * g;
+  const bool f64 = (flags & HYDRO_F64) != 0;
+  const size_t esz = f64 ? 8 : 4;
+  const int nf = (flags & HYDRO_FLUX_MID) ? 3 : 2;
+  const size_t in_b = (size_t)n_groups * 5 * N * N * N * esz;
+  const size_t out_b = (size_t)n_groups * 5 * 4096 * esz;
+  const size_t fl_b = (size_t)n_groups * 3 * nf * 5 * 256 * esz;
+  if (overlap(in, in_b, out, out_b)) return fail(HYDRO_EALIAS, "in and out overlap");
+  if (flux_out && (overlap(flux_out, fl_b, out, out_b) || overlap(flux_out, fl_b, in, in_b)))
+    return fail(HYDRO_EALIAS, "flux_out overlaps in or out");
+  hipStream_t st = (hipStream_t)stream;
+
+  std::lock_guard<std::mutex> lock(g_mu);
+  DeviceState* ds;
+  if (int rc = device_state(&ds)) return rc;
+  Workspace& w = ds->ws[st];
+
+  const bool plain = (flags & HYDRO_PLAIN) || !hy::fused_supported(scheme, reconstruction, riemann,
+                                                                   (flags & HYDRO_CHAR) ? 1 : 0);
+  if (plain) {
+    int grid = n_groups < kPlainGridMax ? n_groups : kPlainGridMax;
+    const long stride = 50L * N * N * N;
+    if (int rc = ensure_plain(w, (size_t)grid * stride * esz)) return rc;
+    hipError_t e;
+    if (f64) {
+      hy::PlainArgs<double> a{(const double*)in, (double*)out, (double*)flux_out, n_groups, g, N, nf,
+                              make_phys<double>(dt, dh, gamma, limiter, flags), (double*)w.plain, stride, ds->diag};
+      e = hy::launch_plain(a, scheme, reconstruction, riemann, grid, st);
+    } else {
+      hy::PlainArgs<float> a{(const float*)in, (float*)out, (float*)flux_out, n_groups, g, N, nf,
+                             make_phys<float>(dt, dh, gamma, limiter, flags), (float*)w.plain, stride, ds->diag};
+      e = hy::launch_plain(a, scheme, reconstruction, riemann, grid, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "plain solver launch");
+    return 0;
+  }
+  // Fused path: a single segment passed by value, host dt included.
+  hy::Seg seg{in, out, flux_out, nullptr, 1.0, dh, 0, n_groups};
+  const int grid = tuned_grid(f64, scheme, reconstruction, riemann, (flags & HYDRO_CHAR) ? 1 : 0, n_groups);
+  if (f64)
+    return run_fused<double>(nullptr, 1, n_groups, g, scheme, reconstruction, riemann, limiter, flags, gamma,
+                             ds->diag, grid, st, &seg, dt);
+  return run_fused<float>(nullptr, 1, n_groups, g, scheme, reconstruction, riemann, limiter, flags, gamma, ds->diag,
+                          grid, st, &seg, dt);
+}
+
+int hydro_solve_batch(const struct hydro_seg* segs, int n_segs, long long n_groups_total,
+                      const struct hydro_spec* spec, void* stream) {
+  g_err[0] = 0;
+  if (!spec) return fail(HYDRO_EINVAL, "null spec");
+  if (int rc = check_options(spec->scheme, spec->reconstruction, spec->riemann, spec->limiter, spec->flags)) return rc;
+  if (spec->flags & HYDRO_PLAIN) return fail(HYDRO_EINVAL, "HYDRO_PLAIN is not a batched path");
+  if (!(spec->gamma > 1.0) || !isfinite(spec->gamma)) return fail(HYDRO_EINVAL, "gamma must exceed 1");
+  if (n_groups_total < 0 || n_segs < 0) return fail(HYDRO_EINVAL, "negative sizes");
+  if (n_groups_total == 0) return 0;
+  if (!segs || n_segs == 0) return fail(HYDRO_EINVAL, "null segment table");
+  const int charlim = (spec->flags & HYDRO_CHAR) ? 1 : 0;
+  if (!hy::fused_supported(spec->scheme, spec->reconstruction, spec->riemann, charlim))
+    return fail(HYDRO_EUNSUPPORTED, "fused path not built for this combination");
+  static_assert(sizeof(hydro_seg) == sizeof(hy::Seg), "segment layout");
+  std::lock_guard<std::mutex> lock(g_mu);
+  DeviceState* ds;
+  if (int rc = device_state(&ds)) return rc;
+  const bool f64 = (spec->flags & HYDRO_F64) != 0;
+  const int g = ghost_width(spec->scheme, spec->reconstruction);
+  const int grid = tuned_grid(f64, spec->scheme, spec->reconstruction, spec->riemann, charlim, n_groups_total);
+  const hy::Seg* sd = (const hy::Seg*)segs;
+  hipStream_t st = (hipStream_t)stream;
+  if (f64)
+    return run_fused<double>(sd, n_segs, n_groups_total, g, spec->scheme, spec->reconstruction, spec->riemann,
+                             spec->limiter, spec->flags, spec->gamma, ds->diag, grid, st);
+  return run_fused<float>(sd, n_segs, n_groups_total, g, spec->scheme, spec->reconstruction, spec->riemann,
+                          spec->limiter, spec->flags, spec->gamma, ds->diag, grid, st);
+}
+
+int hydro_cfl_dt(const void* U, int n_groups, double dh, double gamma, double cfl, int flags, double* dt_out,
+                 void* stream) {
+  g_err[0] = 0;
+  if (n_groups <= 0) return fail(HYDRO_EINVAL, "n_groups must be positive");
+  if (!U || !dt_out) return fail(HYDRO_EINVAL, "null pointer");
+  if (!(dh > 0.0) || !(gamma > 1.0) || !(cfl > 0.0)) return fail(HYDRO_EINVAL, "dh, cfl > 0 and gamma > 1 required");
+  if (flags & ~kKnownFlags) return fail(HYDRO_EINVAL, "unknown flag bits");
+  hipStream_t st = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lock(g_mu);
+  DeviceState* ds;
+  if (int rc = device_state(&ds)) return rc;
+  Workspace& w = ds->ws[st];
+  if (int rc = ensure_partial(w)) return rc;
+  hipError_t e = (flags & HYDRO_F64)
+                     ? hy::launch_maxspeed((const double*)U, n_groups, 4096, gamma, w.partial, kPartials, st)
+                     : hy::launch_maxspeed((const float*)U, n_groups, 4096, gamma, w.partial, kPartials, st);
+  if (e != hipSuccess) return hip_fail(e, "max speed");
+  e = hy::launch_dt_finish(w.partial, kPartials, dh, cfl, dt_out, st);
+  if (e != hipSuccess) return hip_fail(e, "dt finish");
+  return 0;
+}
+
+int hydro_conserved_sums(const void* U, int n_groups, double dh, int flags, double* sums_out, void* stream) {
+  g_err[0] = 0;
+  if (n_groups < 0) return fail(HYDRO_EINVAL, "n_groups < 0");
+  if (!U || !sums_out) return fail(HYDRO_EINVAL, "null pointer");
+  if (!(dh > 0.0)) return fail(HYDRO_EINVAL, "dh must be positive");
+  if (flags & ~kKnownFlags) return fail(HYDRO_EINVAL, "unknown flag bits");
+  hipStream_t st = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lock(g_mu);
+  DeviceState* ds;
+  if (int rc = device_state(&ds)) return rc;
+  Workspace& w = ds->ws[st];
+  if (int rc = ensure_partial(w)) return rc;
+  hipError_t e = (flags & HYDRO_F64)
+                     ? hy::launch_sums((const double*)U, n_groups, 4096, dh, w.partial, kPartials, sums_out, st)
+                     : hy::launch_sums((const float*)U, n_groups, 4096, dh, w.partial, kPartials, sums_out, st);
+  if (e != hipSuccess) return hip_fail(e, "conserved sums");
+  return 0;
+}
+
+int hydro_fill_ghosts_periodic(const void* box, int nx, int ny, int nz, int g, int flags, void* groups_out,
+                               void* stream) {
+  g_err[0] = 0;
+  if (!box || !groups_out) return fail(HYDRO_EINVAL, "null pointer");
+  if (nx <= 0 || ny <= 0 || nz <= 0 || nx % 16 || ny % 16 || nz % 16)
+    return fail(HYDRO_EINVAL, "box sizes must be positive multiples of 16");
+  if (g < 0 || g > 16) return fail(HYDRO_EINVAL, "ghost width out of range");
+  if (flags & ~kKnownFlags) return fail(HYDRO_EINVAL, "unknown flag bits");
+  const size_t esz = (flags & HYDRO_F64) ? 8 : 4;
+  const size_t N = 16 + 2 * g;
+  const size_t nb = (size_t)nx * ny * nz * 5 * esz;
+  const size_t ng = (size_t)(nx / 16) * (ny / 16) * (nz / 16) * 5 * N * N * N * esz;
+  if (overlap(box, nb, groups_out, ng)) return fail(HYDRO_EALIAS, "box and groups overlap");
+  const int grouped = (flags & HYDRO_BOX_GROUPED) ? 1 : 0;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = (flags & HYDRO_F64)
+                     ? hy::launch_fill_periodic((const double*)box, nx, ny, nz, g, grouped, (double*)groups_out, st)
+                     : hy::launch_fill_periodic((const float*)box, nx, ny, nz, g, grouped, (float*)groups_out, st);
+  if (e != hipSuccess) return hip_fail(e, "ghost fill");
+  return 0;
+}
+
+int hydro_fill_groups_interp(const void* coarse, int cn, const int* layout, int n_groups, int g, double base_dh,
+                             int flags, void* groups_out, void* stream) {
+  g_err[0] = 0;
+  if (n_groups < 0) return fail(HYDRO_EINVAL, "n_groups < 0");
+  if (n_groups == 0) return 0;
+  if (!coarse || !layout || !groups_out) return fail(HYDRO_EINVAL, "null pointer");
+  if (cn <= 0 || g < 0 || g > 16 || !(base_dh > 0.0)) return fail(HYDRO_EINVAL, "bad sizes");
+  if (flags & ~kKnownFlags) return fail(HYDRO_EINVAL, "unknown flag bits");
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = (flags & HYDRO_F64)
+                     ? hy::launch_fill_interp((const double*)coarse, cn, layout, n_groups, g, base_dh,
+                                              (double*)groups_out, st)
+                     : hy::launch_fill_interp((const float*)coarse, cn, layout, n_groups, g, base_dh,
+                                              (float*)groups_out, st);
+  if (e != hipSuccess) return hip_fail(e, "interpolating fill");
+  return 0;
+}
+
+int hydro_get_diag(struct hydro_diag* out, int reset, void* stream) {
+  g_err[0] = 0;
+  if (!out) return fail(HYDRO_EINVAL, "null output");
+  hipStream_t st = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lock(g_mu);
+  DeviceState* ds;
+  if (int rc = device_state(&ds)) return rc;
+  unsigned long long h[2];
+  hipError_t e = hipMemcpyAsync(h, ds->diag, sizeof(h), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "diag readback");
+  out->roe_fallbacks = h[0];
+  out->floor_hits = h[1];
+  if (reset) {
+    e = hipMemsetAsync(ds->diag, 0, sizeof(h), st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "diag reset");
+  }
+  return 0;
+}
+
+int hydro_autotune(const struct hydro_spec* spec, int n_groups_hint, void* stream) {
+  g_err[0] = 0;
+  if (!spec) return fail(HYDRO_EINVAL, "null spec");
+  if (int rc = check_options(spec->scheme, spec->reconstruction, spec->riemann, spec->limiter, spec->flags)) return rc;
+  const int charlim = (spec->flags & HYDRO_CHAR) ? 1 : 0;
+  if (!hy::fused_supported(spec->scheme, spec->reconstruction, spec->riemann, charlim))
+    return fail(HYDRO_EUNSUPPORTED, "fused path not built for this combination");
+  if (n_groups_hint <= 0) return fail(HYDRO_EINVAL, "n_groups_hint must be positive");
+  const bool f64 = (spec->flags & HYDRO_F64) != 0;
+  const int g = ghost_width(spec->scheme, spec->reconstruction);
+  const size_t N = 16 + 2 * g;
+  const size_t esz = f64 ? 8 : 4;
+  const long long n = n_groups_hint;
+  hipStream_t st = (hipStream_t)stream;
+  // Synthetic uniform state at rest (rho = 1, p = 1): every path is taken
+  // with the same instruction mix, so timings compare launch shapes only.
+  void *in = nullptr, *out = nullptr;
+  double* dtd = nullptr;
+  hy::Seg* sd = nullptr;
+  hipError_t e = hipMalloc(&in, (size_t)n * 5 * N * N * N * esz);
+  if (e == hipSuccess) e = hipMalloc(&out, (size_t)n * 5 * 4096 * esz);
+  if (e == hipSuccess) e = hipMalloc((void**)&dtd, sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&sd, sizeof(hy::Seg));
+  if (e != hipSuccess) {
+    hipFree(in); hipFree(out); hipFree(dtd); hipFree(sd);
+    return hip_fail(e, "autotune buffers");
+  }
+  {
+    const size_t nc = N * N * N;
+    std::vector<char> host(5 * nc * esz);
+    for (size_t q = 0; q < nc; ++q) {
+      double v[5] = {1.0, 0.0, 0.0, 0.0, 1.0 / (spec->gamma - 1.0)};
+      for (int k = 0; k < 5; ++k) {
+        if (f64) ((double*)host.data())[k * nc + q] = v[k];
+        else ((float*)host.data())[k * nc + q] = (float)v[k];
+      }
+    }
+    for (long long q = 0; q < n && e == hipSuccess; ++q)
+      e = hipMemcpyAsync((char*)in + q * host.size(), host.data(), host.size(), hipMemcpyHostToDevice, st);
+    double dt = 1e-4;
+    hy::Seg s{in, out, nullptr, dtd, 1.0, 1.0 / 256, 0, n};
+    if (e == hipSuccess) e = hipMemcpyAsync(dtd, &dt, sizeof(dt), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(sd, &s, sizeof(s), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+  }
+  int cus = 256;
+  {
+    hipDeviceProp_t prop;
+    int dev;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+      cus = prop.multiProcessorCount;
+  }
+  DeviceState* ds = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_mu);
+    if (int rc = device_state(&ds)) { hipFree(in); hipFree(out); hipFree(dtd); hipFree(sd); return rc; }
+  }
+  const int mults[] = {1, 2, 3, 4, 6, 8, 12, 16};
+  int best = -1;
+  float best_ms = 1e30f;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  for (int m : mults) {
+    if (e != hipSuccess) break;
+    long long grid = (long long)cus * m;
+    if (grid > n) grid = n;
+    float ms_min = 1e30f;
+    for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
+      e = hipEventRecord(e0, st);
+      int rc = f64 ? run_fused<double>(sd, 1, n, g, spec->scheme, spec->reconstruction, spec->riemann, spec->limiter,
+                                       spec->flags, spec->gamma, ds->diag, (int)grid, st)
+                   : run_fused<float>(sd, 1, n, g, spec->scheme, spec->reconstruction, spec->riemann, spec->limiter,
+                                      spec->flags, spec->gamma, ds->diag, (int)grid, st);
+      if (rc) { e = hipErrorLaunchFailure; break; }
+      if (e == hipSuccess) e = hipEventRecord(e1, st);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (rep > 0 && ms < ms_min) ms_min = ms;  // first launch is a warm-up
+    }
+    if (ms_min < best_ms) { best_ms = ms_min; best = (int)grid; }
+    if (grid == n) break;
+  }
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  hipFree(in); hipFree(out); hipFree(dtd); hipFree(sd);
+  if (e != hipSuccess || best < 0) return hip_fail(e == hipSuccess ? hipErrorUnknown : e, "autotune");
+  std::lock_guard<std::mutex> lock(g_mu);
+  tune_load();
+  const std::string key = tune_key(f64, spec->scheme, spec->reconstruction, spec->riemann, charlim);
+  g_tune[key] = best;
+  if (const char* path = getenv("HYDRO_TUNE_CACHE")) {
+    if (FILE* f = fopen(path, "a")) {
+      fprintf(f, "%s %d\n", key.c_str(), best);
+      fclose(f);
+    }
+  }
+  return best;
+}
+
+void hydro_shutdown(void) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  hipDeviceSynchronize();
+  for (auto& kv : g_dev) {
+    int prev = 0;
+    hipGetDevice(&prev);
+    hipSetDevice(kv.first);
+    for (auto& w : kv.second.ws) {
+      if (w.second.plain) hipFree(w.second.plain);
+      if (w.second.partial) hipFree(w.second.partial);
+    }
+    if (kv.second.diag) hipFree(kv.second.diag);
+    hipSetDevice(prev);
+  }
+  g_dev.clear();
+  g_tune.clear();
+  g_tune_loaded = false;
+}
+
+}  // extern "C"

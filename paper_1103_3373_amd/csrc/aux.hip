@@ -1,0 +1,261 @@
+// Auxiliary kernels around the solver:
+//  * preparation step (paper Sec. 4.2): periodic ghost fill of patch groups
+//    from a resident box, and trilinear fill of AMR-shaped groups from a
+//    coarse field (spatial interpolation at coarse-fine boundaries);
+//  * FP64 CFL time step: max signal speed per block (wave64 shuffles), then a
+//    single-block finish, dt = cfl * dh / max (max is order-free, so the
+//    result is deterministic and equals a serial evaluation bit for bit);
+//  * FP64 conserved sums with a fixed two-level reduction order.
+#include "hydro_internal.h"
+
+namespace hy {
+
+// ---------------------------------------------------------------------------
+// Periodic ghost fill.  Output groups [G][5][N][N][N], G = (gz*ngy+gy)*ngx+gx.
+// Source either a plain box [5][nz][ny][nx] or the grouped interior layout
+// [G][5][16][16][16] (grouped != 0).  One thread per output cell, x fastest.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) fill_periodic_kernel(const T* __restrict__ box, int nx, int ny, int nz, int g,
+                                                            int grouped, T* __restrict__ out, long long total) {
+  const int N = 16 + 2 * g;
+  const long long nc = (long long)N * N * N;
+  const int ngx = nx >> 4, ngy = ny >> 4;
+  const long long boxc = (long long)nx * ny * nz;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
+       t += (long long)gridDim.x * blockDim.x) {
+    const long long G = t / nc;
+    const int r = (int)(t - G * nc);
+    const int i = r % N, j = (r / N) % N, k = r / (N * N);
+    const int gx = (int)(G % ngx), gy = (int)((G / ngx) % ngy), gz = (int)(G / ((long long)ngx * ngy));
+    int sx = gx * 16 + i - g, sy = gy * 16 + j - g, sz = gz * 16 + k - g;
+    sx += (sx < 0) ? nx : 0; sx -= (sx >= nx) ? nx : 0;
+    sy += (sy < 0) ? ny : 0; sy -= (sy >= ny) ? ny : 0;
+    sz += (sz < 0) ? nz : 0; sz -= (sz >= nz) ? nz : 0;
+    T* o = out + G * 5 * nc + r;
+    if (grouped) {
+      const long long sg = ((long long)(sz >> 4) * ngy + (sy >> 4)) * ngx + (sx >> 4);
+      const T* s = box + sg * 5 * 4096 + (((sz & 15) * 16 + (sy & 15)) * 16 + (sx & 15));
+#pragma unroll
+      for (int n = 0; n < 5; ++n) o[n * nc] = s[n * 4096];
+    } else {
+      const T* s = box + ((long long)sz * ny + sy) * nx + sx;
+#pragma unroll
+      for (int n = 0; n < 5; ++n) o[n * nc] = s[n * boxc];
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_fill_periodic(const T* box, int nx, int ny, int nz, int g, int grouped, T* out, hipStream_t st) {
+  const int N = 16 + 2 * g;
+  const long long total = (long long)(nx / 16) * (ny / 16) * (nz / 16) * N * N * N;
+  if (total == 0) return hipSuccess;
+  long long blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  fill_periodic_kernel<T><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(box, nx, ny, nz, g, grouped, out, total);
+  return hipGetLastError();
+}
+template hipError_t launch_fill_periodic<float>(const float*, int, int, int, int, int, float*, hipStream_t);
+template hipError_t launch_fill_periodic<double>(const double*, int, int, int, int, int, double*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// AMR-shaped preparation: every cell of every padded group is the trilinear
+// interpolation, at its centre, of a periodic coarse field [5][cn][cn][cn]
+// on the unit box.  layout[G] = (level, ox, oy, oz): the group's first
+// interior cell on the level-l grid of spacing base_dh / 2^l.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) fill_interp_kernel(const T* __restrict__ coarse, int cn,
+                                                          const int4* __restrict__ layout, int g, double base_dh,
+                                                          T* __restrict__ out, long long total) {
+  const int N = 16 + 2 * g;
+  const long long nc = (long long)N * N * N;
+  const long long cc = (long long)cn * cn * cn;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
+       t += (long long)gridDim.x * blockDim.x) {
+    const long long G = t / nc;
+    const int r = (int)(t - G * nc);
+    const int i = r % N, j = (r / N) % N, k = r / (N * N);
+    const int4 L = layout[G];
+    const double dh = base_dh / (double)(1 << L.x);
+    // Coarse-index coordinates of the fine cell centre.
+    const double X = ((double)(L.y + i - g) + 0.5) * dh * cn - 0.5;
+    const double Y = ((double)(L.z + j - g) + 0.5) * dh * cn - 0.5;
+    const double Z = ((double)(L.w + k - g) + 0.5) * dh * cn - 0.5;
+    const double fx0 = floor(X), fy0 = floor(Y), fz0 = floor(Z);
+    const double ax = X - fx0, ay = Y - fy0, az = Z - fz0;
+    int x0 = (int)fx0, y0 = (int)fy0, z0 = (int)fz0;
+    x0 = ((x0 % cn) + cn) % cn; y0 = ((y0 % cn) + cn) % cn; z0 = ((z0 % cn) + cn) % cn;
+    const int x1 = (x0 + 1) % cn, y1 = (y0 + 1) % cn, z1 = (z0 + 1) % cn;
+    const long long c000 = ((long long)z0 * cn + y0) * cn + x0, c001 = ((long long)z0 * cn + y0) * cn + x1;
+    const long long c010 = ((long long)z0 * cn + y1) * cn + x0, c011 = ((long long)z0 * cn + y1) * cn + x1;
+    const long long c100 = ((long long)z1 * cn + y0) * cn + x0, c101 = ((long long)z1 * cn + y0) * cn + x1;
+    const long long c110 = ((long long)z1 * cn + y1) * cn + x0, c111 = ((long long)z1 * cn + y1) * cn + x1;
+    T* o = out + G * 5 * nc + r;
+#pragma unroll
+    for (int n = 0; n < 5; ++n) {
+      const T* f = coarse + n * cc;
+      const double v00 = (1.0 - ax) * (double)f[c000] + ax * (double)f[c001];
+      const double v01 = (1.0 - ax) * (double)f[c010] + ax * (double)f[c011];
+      const double v10 = (1.0 - ax) * (double)f[c100] + ax * (double)f[c101];
+      const double v11 = (1.0 - ax) * (double)f[c110] + ax * (double)f[c111];
+      const double v0 = (1.0 - ay) * v00 + ay * v01;
+      const double v1 = (1.0 - ay) * v10 + ay * v11;
+      o[n * nc] = (T)((1.0 - az) * v0 + az * v1);
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_fill_interp(const T* coarse, int cn, const int* layout, long long n_groups, int g, double base_dh,
+                              T* out, hipStream_t st) {
+  const int N = 16 + 2 * g;
+  const long long total = n_groups * N * N * N;
+  if (total == 0) return hipSuccess;
+  long long blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  fill_interp_kernel<T><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(coarse, cn, (const int4*)layout, g, base_dh,
+                                                                      out, total);
+  return hipGetLastError();
+}
+template hipError_t launch_fill_interp<float>(const float*, int, const int*, long long, int, double, float*,
+                                              hipStream_t);
+template hipError_t launch_fill_interp<double>(const double*, int, const int*, long long, int, double, double*,
+                                               hipStream_t);
+
+// ---------------------------------------------------------------------------
+// FP64 signal speed and time step.  The per-cell expression is evaluated in
+// double without contraction, in a fixed order, so that the maximum (and
+// hence dt) is bit-identical to a serial FP64 evaluation on the same data.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <typename T>
+__device__ __attribute__((noinline)) double cell_signal_speed(const T* u, long long cells, double gamma) {
+#pragma clang fp contract(off)
+  const double rho = (double)u[0];
+  const double mx = (double)u[cells], my = (double)u[2 * cells], mz = (double)u[3 * cells];
+  const double vx = mx / rho, vy = my / rho, vz = mz / rho;
+  const double ke = 0.5 * (mx * vx + my * vy + mz * vz);
+  const double p = (gamma - 1.0) * ((double)u[4 * cells] - ke);
+  const double cs = __builtin_sqrt(gamma * p / rho);
+  double av = __builtin_fabs(vx);
+  if (__builtin_fabs(vy) > av) av = __builtin_fabs(vy);
+  if (__builtin_fabs(vz) > av) av = __builtin_fabs(vz);
+  return av + cs;
+}
+
+// U: n_blocks blocks of [5][cells]; one partial max per workgroup.
+template <typename T>
+__global__ void __launch_bounds__(256) maxspeed_kernel(const T* __restrict__ U, long long n_blocks, long long cells,
+                                                       double gamma, double* __restrict__ partial) {
+  __shared__ double red[4];
+  double m = 0.0;
+  const long long total = n_blocks * cells;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
+       t += (long long)gridDim.x * blockDim.x) {
+    const long long b = t / cells, q = t - b * cells;
+    const double s = cell_signal_speed(U + b * 5 * cells + q, cells, gamma);
+    m = s > m ? s : m;
+  }
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+__global__ void __launch_bounds__(256) dt_finish_kernel(const double* __restrict__ partial, int n, double dh,
+                                                        double cfl, double* __restrict__ dt_out) {
+#pragma clang fp contract(off)
+  __shared__ double red[4];
+  double m = 0.0;
+  for (int t = threadIdx.x; t < n; t += blockDim.x) m = fmax(m, partial[t]);
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    dt_out[0] = cfl * dh / mx;
+  }
+}
+
+template <typename T>
+hipError_t launch_maxspeed(const T* U, long long n_blocks, long long cells, double gamma, double* partial,
+                           int n_partial, hipStream_t st) {
+  maxspeed_kernel<T><<<dim3(n_partial), dim3(256), 0, st>>>(U, n_blocks, cells, gamma, partial);
+  return hipGetLastError();
+}
+template hipError_t launch_maxspeed<float>(const float*, long long, long long, double, double*, int, hipStream_t);
+template hipError_t launch_maxspeed<double>(const double*, long long, long long, double, double*, int, hipStream_t);
+
+hipError_t launch_dt_finish(const double* partial, int n_partial, double dh, double cfl, double* dt_out,
+                            hipStream_t st) {
+  dt_finish_kernel<<<dim3(1), dim3(256), 0, st>>>(partial, n_partial, dh, cfl, dt_out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// FP64 conserved sums.  Workgroup w sums a fixed contiguous slice of cells
+// (lane-strided, then a fixed shuffle tree); a single workgroup then adds the
+// partials in index order.  The order depends only on n_partial, never on
+// timing, so repeated calls are bitwise identical.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) sums_kernel(const T* __restrict__ U, long long n_blocks, long long cells,
+                                                   double* __restrict__ partial) {
+  __shared__ double red[5][4];
+  const long long total = n_blocks * cells;
+  const long long per = (total + gridDim.x - 1) / gridDim.x;
+  const long long lo = blockIdx.x * per, hi = min(total, lo + per);
+  double s[5] = {0, 0, 0, 0, 0};
+  for (long long t = lo + threadIdx.x; t < hi; t += blockDim.x) {
+    const long long b = t / cells, q = t - b * cells;
+    const T* u = U + b * 5 * cells + q;
+#pragma unroll
+    for (int n = 0; n < 5; ++n) s[n] += (double)u[n * cells];
+  }
+#pragma unroll
+  for (int n = 0; n < 5; ++n) {
+    double v = wave_sum(s[n]);
+    if ((threadIdx.x & 63) == 0) red[n][threadIdx.x >> 6] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 5) {
+    const int n = threadIdx.x;
+    partial[(long long)blockIdx.x * 5 + n] = (red[n][0] + red[n][1]) + (red[n][2] + red[n][3]);
+  }
+}
+
+__global__ void __launch_bounds__(64) sums_finish_kernel(const double* __restrict__ partial, int n, double vol,
+                                                         double* __restrict__ out) {
+  if (threadIdx.x < 5) {
+    double s = 0.0;
+    for (int b = 0; b < n; ++b) s += partial[(long long)b * 5 + threadIdx.x];
+    out[threadIdx.x] = s * vol;
+  }
+}
+
+template <typename T>
+hipError_t launch_sums(const T* U, long long n_blocks, long long cells, double dh, double* partial, int n_partial,
+                       double* sums_out, hipStream_t st) {
+  sums_kernel<T><<<dim3(n_partial), dim3(256), 0, st>>>(U, n_blocks, cells, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  sums_finish_kernel<<<dim3(1), dim3(64), 0, st>>>(partial, n_partial, dh * dh * dh, sums_out);
+  return hipGetLastError();
+}
+template hipError_t launch_sums<float>(const float*, long long, long long, double, double*, int, double*, hipStream_t);
+template hipError_t launch_sums<double>(const double*, long long, long long, double, double*, int, double*,
+                                        hipStream_t);
+
+}  // namespace hy

@@ -1,0 +1,83 @@
+// Internal interfaces between the C-ABI host code and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hydro_math.hpp"
+
+namespace hy {
+
+template <typename T>
+struct PlainArgs {
+  const T* in;     // [n][5][N][N][N]
+  T* out;          // [n][5][16][16][16]
+  T* flux;         // [n][3][nf][5][16][16] or null
+  long n_groups;
+  int g, N, nf;
+  Phys<T> ph;
+  T* ws;           // per-workgroup global temporaries
+  long ws_stride;  // elements per workgroup (50 N^3)
+  unsigned long long* diag;  // [0] Roe fallbacks, [1] floor activations
+};
+
+hipError_t launch_plain(const PlainArgs<float>& a, int scheme, int recon, int riemann, int grid, hipStream_t st);
+hipError_t launch_plain(const PlainArgs<double>& a, int scheme, int recon, int riemann, int grid, hipStream_t st);
+
+// Segment of a batched launch: a run of groups sharing in/out/flux arrays,
+// dh and a device time step (scaled per level).
+struct Seg {
+  const void* in;
+  void* out;
+  void* flux;
+  const double* dt;
+  double dt_scale;
+  double dh;
+  long long first;   // first global group index of this segment
+  long long count;
+};
+
+// Fused (optimized) solver.  groups are addressed through segments; a plain
+// single-array call is one segment.
+template <typename T>
+struct FusedArgs {
+  const Seg* segs;   // device table
+  int n_segs;
+  long long n_groups;
+  int g, nf;
+  T gamma, theta, floor;
+  int limiter, charlim, roe_fb_hllc;
+  unsigned long long* diag;
+  // Single-segment launches pass their segment and time step by value
+  // (segs == nullptr), so no table upload is needed.
+  Seg seg0;
+  double dt0;
+};
+
+struct FusedCfg {
+  int grid;          // number of workgroups (persistent)
+};
+
+bool fused_supported(int scheme, int recon, int riemann, int charlim);
+hipError_t launch_fused(const FusedArgs<float>& a, int scheme, int recon, int riemann, const FusedCfg& cfg,
+                        hipStream_t st);
+hipError_t launch_fused(const FusedArgs<double>& a, int scheme, int recon, int riemann, const FusedCfg& cfg,
+                        hipStream_t st);
+int fused_block_threads();
+
+// Auxiliary kernels.
+template <typename T>
+hipError_t launch_fill_periodic(const T* box, int nx, int ny, int nz, int g, int grouped, T* out, hipStream_t st);
+template <typename T>
+hipError_t launch_fill_interp(const T* coarse, int cn, const int* layout, long long n_groups, int g, double base_dh,
+                              T* out, hipStream_t st);
+template <typename T>
+hipError_t launch_maxspeed(const T* U, long long n_blocks, long long cells, double gamma, double* partial,
+                           int n_partial, hipStream_t st);
+hipError_t launch_dt_finish(const double* partial, int n_partial, double dh, double cfl, double* dt_out,
+                            hipStream_t st);
+template <typename T>
+hipError_t launch_sums(const T* U, long long n_blocks, long long cells, double dh, double* partial, int n_partial,
+                       double* sums_out, hipStream_t st);
+
+}  // namespace hy

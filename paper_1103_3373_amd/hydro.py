@@ -1,0 +1,235 @@
+"""Python binding of the C ABI in include/hydro.h (ctypes; argument
+marshalling only -- every step of the solver runs in the HIP library).
+
+Device buffers are torch tensors on a HIP device; the current torch stream is
+passed to every call.  The library must be built (``__graft_entry__.build()``
+or ``python -m paper_1103_3373_amd.build``); if ``libhydro.so`` is missing or
+cannot be loaded, every call raises -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhydro.so")
+
+MHM, VL, CTU = 0, 1, 2
+PLM, PPM = 0, 1
+ROE, HLLC, HLLE = 0, 1, 2
+GMINMOD, VANLEER, VANALBADA, HYBRID = 0, 1, 2, 3
+F64, CHAR, FLUX_MID, PLAIN, ROE_FB_HLLC, BOX_GROUPED = 0x01, 0x02, 0x04, 0x08, 0x10, 0x20
+
+EXPORTS = (
+    "hydro_ghost_width", "hydro_solve_groups", "hydro_cfl_dt", "hydro_conserved_sums",
+    "hydro_fill_ghosts_periodic", "hydro_fill_groups_interp", "hydro_solve_batch", "hydro_autotune",
+    "hydro_get_diag", "hydro_last_error", "hydro_shutdown",
+)
+
+
+class HydroError(RuntimeError):
+    def __init__(self, fn: str, code: int, msg: str):
+        super().__init__(f"{fn} failed ({code}): {msg}")
+        self.code = code
+
+
+class Seg(ctypes.Structure):
+    _fields_ = [("in_", ctypes.c_void_p), ("out", ctypes.c_void_p), ("flux", ctypes.c_void_p),
+                ("dt", ctypes.c_void_p), ("dt_scale", ctypes.c_double), ("dh", ctypes.c_double),
+                ("first", ctypes.c_longlong), ("count", ctypes.c_longlong)]
+
+
+class Spec(ctypes.Structure):
+    _fields_ = [("scheme", ctypes.c_int), ("reconstruction", ctypes.c_int), ("riemann", ctypes.c_int),
+                ("limiter", ctypes.c_int), ("flags", ctypes.c_int), ("gamma", ctypes.c_double)]
+
+
+class Diag(ctypes.Structure):
+    _fields_ = [("roe_fallbacks", ctypes.c_ulonglong), ("floor_hits", ctypes.c_ulonglong)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libhydro.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing (run __graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i, d, ll = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_longlong
+    L.hydro_ghost_width.argtypes = [i, i]
+    L.hydro_ghost_width.restype = i
+    L.hydro_solve_groups.argtypes = [P, P, P, i, d, d, d, i, i, i, i, i, P]
+    L.hydro_solve_groups.restype = i
+    L.hydro_cfl_dt.argtypes = [P, i, d, d, d, i, P, P]
+    L.hydro_cfl_dt.restype = i
+    L.hydro_conserved_sums.argtypes = [P, i, d, i, P, P]
+    L.hydro_conserved_sums.restype = i
+    L.hydro_fill_ghosts_periodic.argtypes = [P, i, i, i, i, i, P, P]
+    L.hydro_fill_ghosts_periodic.restype = i
+    L.hydro_fill_groups_interp.argtypes = [P, i, P, i, i, d, i, P, P]
+    L.hydro_fill_groups_interp.restype = i
+    L.hydro_solve_batch.argtypes = [P, i, ll, ctypes.POINTER(Spec), P]
+    L.hydro_solve_batch.restype = i
+    L.hydro_autotune.argtypes = [ctypes.POINTER(Spec), i, P]
+    L.hydro_autotune.restype = i
+    L.hydro_get_diag.argtypes = [ctypes.POINTER(Diag), i, P]
+    L.hydro_get_diag.restype = i
+    L.hydro_last_error.argtypes = []
+    L.hydro_last_error.restype = ctypes.c_char_p
+    L.hydro_shutdown.argtypes = []
+    L.hydro_shutdown.restype = None
+    _lib = L
+    return L
+
+
+def _check(fn: str, rc: int) -> int:
+    if rc < 0:
+        raise HydroError(fn, rc, lib().hydro_last_error().decode())
+    return rc
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _dtype_flag(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return 0
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _require(t: torch.Tensor, name: str, shape=None, dtype=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+def ghost_width(scheme: int, recon: int) -> int:
+    return _check("hydro_ghost_width", lib().hydro_ghost_width(scheme, recon))
+
+
+def solve_groups(inp, out, flux=None, *, dt, dh, gamma, scheme, recon, riemann, limiter=VANLEER, char=False,
+                 plain=False, flux_mid=False, roe_fb_hllc=False, stream=None):
+    """One step of n patch groups: inp [n,5,N,N,N] -> out [n,5,16,16,16]."""
+    n = inp.shape[0]
+    N = 16 + 2 * ghost_width(scheme, recon)
+    _require(inp, "inp", (n, 5, N, N, N))
+    _require(out, "out", (n, 5, 16, 16, 16), inp.dtype)
+    if flux is not None:
+        _require(flux, "flux", (n, 3, 3 if flux_mid else 2, 5, 16, 16), inp.dtype)
+    flags = _dtype_flag(inp) | (CHAR if char else 0) | (PLAIN if plain else 0) | (FLUX_MID if flux_mid else 0) \
+        | (ROE_FB_HLLC if roe_fb_hllc else 0)
+    _check("hydro_solve_groups", lib().hydro_solve_groups(
+        _ptr(inp), _ptr(out), _ptr(flux), n, float(dt), float(dh), float(gamma), scheme, recon, riemann, limiter,
+        flags, _stream(stream)))
+    return out
+
+
+def cfl_dt(U, dh, gamma, cfl, dt_out=None, stream=None):
+    """FP64 dt from interiors U [n,5,16,16,16] into a device double tensor."""
+    _require(U, "U")
+    if dt_out is None:
+        dt_out = torch.empty(1, dtype=torch.float64, device=U.device)
+    _check("hydro_cfl_dt", lib().hydro_cfl_dt(_ptr(U), U.shape[0], float(dh), float(gamma), float(cfl),
+                                              _dtype_flag(U), _ptr(dt_out), _stream(stream)))
+    return dt_out
+
+
+def conserved_sums(U, dh, sums_out=None, stream=None):
+    _require(U, "U")
+    if sums_out is None:
+        sums_out = torch.empty(5, dtype=torch.float64, device=U.device)
+    _check("hydro_conserved_sums", lib().hydro_conserved_sums(_ptr(U), U.shape[0], float(dh), _dtype_flag(U),
+                                                              _ptr(sums_out), _stream(stream)))
+    return sums_out
+
+
+def fill_ghosts_periodic(box, g, out=None, *, grouped=False, shape=None, stream=None):
+    """Ghosted groups from a periodic box [5,nz,ny,nx] (or grouped [G,5,16,16,16]
+    with shape=(nx, ny, nz))."""
+    _require(box, "box")
+    if grouped:
+        nx, ny, nz = shape
+    else:
+        _, nz, ny, nx = box.shape
+    N = 16 + 2 * g
+    G = (nx // 16) * (ny // 16) * (nz // 16)
+    if out is None:
+        out = torch.empty((G, 5, N, N, N), dtype=box.dtype, device=box.device)
+    _require(out, "out", (G, 5, N, N, N), box.dtype)
+    flags = _dtype_flag(box) | (BOX_GROUPED if grouped else 0)
+    _check("hydro_fill_ghosts_periodic", lib().hydro_fill_ghosts_periodic(_ptr(box), nx, ny, nz, g, flags,
+                                                                          _ptr(out), _stream(stream)))
+    return out
+
+
+def fill_groups_interp(coarse, layout, g, base_dh, out=None, stream=None):
+    """AMR-shaped groups by trilinear interpolation of coarse [5,cn,cn,cn];
+    layout int32 [n,4] = (level, ox, oy, oz)."""
+    _require(coarse, "coarse")
+    _require(layout, "layout", dtype=torch.int32)
+    n = layout.shape[0]
+    N = 16 + 2 * g
+    if out is None:
+        out = torch.empty((n, 5, N, N, N), dtype=coarse.dtype, device=coarse.device)
+    _check("hydro_fill_groups_interp", lib().hydro_fill_groups_interp(
+        _ptr(coarse), coarse.shape[1], _ptr(layout), n, g, float(base_dh), _dtype_flag(coarse), _ptr(out),
+        _stream(stream)))
+    return out
+
+
+def make_spec(scheme, recon, riemann, limiter=VANLEER, *, gamma, char=False, f64=False, flux_mid=False,
+              roe_fb_hllc=False) -> Spec:
+    flags = (F64 if f64 else 0) | (CHAR if char else 0) | (FLUX_MID if flux_mid else 0) \
+        | (ROE_FB_HLLC if roe_fb_hllc else 0)
+    return Spec(scheme, recon, riemann, limiter, flags, float(gamma))
+
+
+def seg_table(segs, device) -> torch.Tensor:
+    """Pack hydro_seg records [(in, out, flux|None, dt_tensor, dt_scale, dh, first, count)]
+    into a device byte tensor."""
+    arr = (Seg * len(segs))()
+    for q, (i, o, f, dtt, sc, dh, first, count) in enumerate(segs):
+        arr[q] = Seg(i.data_ptr(), o.data_ptr(), 0 if f is None else f.data_ptr(), dtt.data_ptr(), float(sc),
+                     float(dh), int(first), int(count))
+    host = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8)
+    return host.to(device)
+
+
+def solve_batch(seg_dev: torch.Tensor, n_segs: int, n_groups_total: int, spec: Spec, stream=None):
+    _check("hydro_solve_batch", lib().hydro_solve_batch(_ptr(seg_dev), n_segs, int(n_groups_total),
+                                                        ctypes.byref(spec), _stream(stream)))
+
+
+def autotune(spec: Spec, n_groups_hint: int, stream=None) -> int:
+    return _check("hydro_autotune", lib().hydro_autotune(ctypes.byref(spec), int(n_groups_hint), _stream(stream)))
+
+
+def get_diag(reset=False, stream=None) -> dict:
+    d = Diag()
+    _check("hydro_get_diag", lib().hydro_get_diag(ctypes.byref(d), 1 if reset else 0, _stream(stream)))
+    return {"roe_fallbacks": int(d.roe_fallbacks), "floor_hits": int(d.floor_hits)}
+
+
+def shutdown():
+    lib().hydro_shutdown()

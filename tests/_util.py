@@ -1,0 +1,47 @@
+"""Shared test helpers (no solver arithmetic)."""
+import numpy as np
+
+from paper_1103_3373_amd import workloads as W
+
+
+def random_smooth_box(n, gamma, seed, amp=0.2, ny=None, nz=None):
+    """Smooth positive random state (a few low Fourier modes) on a periodic box."""
+    ny = n if ny is None else ny
+    nz = n if nz is None else nz
+    rng = np.random.default_rng(seed)
+    x = (np.arange(n) + 0.5) / n
+    y = (np.arange(ny) + 0.5) / ny
+    z = (np.arange(nz) + 0.5) / nz
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    fields = []
+    for _ in range(5):
+        f = np.zeros_like(X)
+        for _ in range(3):
+            k = rng.integers(-2, 3, size=3)
+            ph = rng.uniform(0, 2 * np.pi)
+            f += rng.uniform(-1, 1) * np.cos(2 * np.pi * (k[0] * X + k[1] * Y + k[2] * Z) + ph)
+        fields.append(f)
+    rho = 1.0 + amp * fields[0] / 3
+    p = 1.0 + amp * fields[4] / 3
+    return W.primitive_to_conserved(rho, amp * fields[1], amp * fields[2], amp * fields[3], p, gamma)
+
+
+def rel_errors(a, b):
+    """Per-variable (rel_L1, rel_Linf) of a against reference b; arrays [..., 5, ...]
+    with the variable on axis 1 (groups) or 0 (box)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    ax = 1 if a.ndim in (5, 6) else 0
+    a = np.moveaxis(a, ax, 0).reshape(5, -1) if a.shape[ax] == 5 else a.reshape(1, -1)
+    b = np.moveaxis(b, ax, 0).reshape(5, -1) if b.shape[ax] == 5 else b.reshape(1, -1)
+    d = np.abs(a - b)
+    l1 = d.sum(1) / np.maximum(np.abs(b).sum(1), 1e-300)
+    linf = d.max(1) / np.maximum(np.abs(b).max(1), 1e-300)
+    return l1, linf
+
+
+def scaled_max_err(a, b):
+    """max |a-b| / max |b| over the whole array (one number)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))

@@ -1,0 +1,85 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and rejects bad arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hydro.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(hydro_[a-z_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1103_3373_amd import hydro
+    return hydro.lib()
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for n in ("hydro_solve_groups", "hydro_cfl_dt", "hydro_conserved_sums", "hydro_fill_ghosts_periodic",
+              "hydro_solve_batch", "hydro_autotune", "hydro_get_diag", "hydro_last_error", "hydro_shutdown",
+              "hydro_ghost_width", "hydro_fill_groups_interp"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def test_binding_covers_exports():
+    from paper_1103_3373_amd import hydro
+    assert sorted(hydro.EXPORTS) == _declared()
+
+
+def test_ghost_widths(L):
+    assert [L.hydro_ghost_width(s, r) for s in (0, 1, 2) for r in (0, 1)] == [2, 3, 3, 4, 2, 3]
+    assert L.hydro_ghost_width(3, 0) == -1 and L.hydro_ghost_width(0, 2) == -1
+
+
+def _solve(L, *, inp=0x1000, out=0x100000000, flux=None, n=1, dt=1e-3, dh=1.0, gamma=1.4, scheme=2, recon=1,
+           riemann=1, limiter=1, flags=0):
+    return L.hydro_solve_groups(ctypes.c_void_p(inp), ctypes.c_void_p(out), ctypes.c_void_p(flux), n, dt, dh, gamma,
+                                scheme, recon, riemann, limiter, flags, None)
+
+
+def test_argument_validation(L):
+    EINVAL, EUNSUP, EALIAS = -1, -2, -4
+    assert _solve(L, n=0) == 0  # empty batch is a no-op
+    assert _solve(L, n=-1) == EINVAL
+    assert _solve(L, dt=0.0) == EINVAL
+    assert _solve(L, dt=float("nan")) == EINVAL
+    assert _solve(L, dh=-1.0) == EINVAL
+    assert _solve(L, gamma=1.0) == EINVAL
+    assert _solve(L, scheme=3) == EINVAL
+    assert _solve(L, recon=2) == EINVAL
+    assert _solve(L, riemann=3) == EUNSUP  # exact solver: oracle only
+    assert _solve(L, riemann=4) == EINVAL
+    assert _solve(L, limiter=4) == EINVAL
+    assert _solve(L, flags=0x100) == EINVAL
+    assert _solve(L, inp=0, out=0x2000) == EINVAL
+    # in [0x1000, 0x1000 + 5*22^3*4) overlaps out
+    assert _solve(L, inp=0x1000, out=0x1000 + 4096) == EALIAS
+    assert _solve(L, inp=0x1000, out=0x100000000, flux=0x100000000 + 64) == EALIAS
+    assert L.hydro_last_error()  # message recorded
+    assert L.hydro_fill_ghosts_periodic(ctypes.c_void_p(0x1000), 24, 16, 16, 2, 0, ctypes.c_void_p(0x100000000),
+                                        None) == EINVAL
+    assert L.hydro_cfl_dt(ctypes.c_void_p(0x1000), 0, 1.0, 1.4, 0.5, 0, ctypes.c_void_p(0x2000), None) == EINVAL
+
+
+def test_product_path_does_not_import_oracle():
+    """The HIP binding and package never reference the oracle."""
+    pkg = os.path.join(ROOT, "paper_1103_3373_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".hpp", ".cpp")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in src and "from oracle" not in src and "oracle/" not in src, f
