@@ -1,0 +1,274 @@
+"""Benchmark: cell updates per second of the unsplit CTU solver at 256^3.
+
+Workload (one GPU): a 256^3 periodic box as 4096 patch groups of 16^3
+interior cells plus 3 ghost cells, FP32, CTU + PPM (characteristic
+limiting, van Leer) + HLLC, gamma = 1.4, seeded lognormal density with
+Mach-1 smooth velocities and 4 blasts (p = 100, r = 8 cells).
+
+One step is the whole hot path, all on the device with the state resident
+in HBM:
+  a0  periodic ghost fill of the 4096 groups from the resident state,
+  a1-a8, a11  one persistent batched launch of the fused solver (the time
+      step is read from device memory),
+  a9  FP64 CFL time step of the new state (device double, used next step),
+  a10 FP64 conserved sums of the new state.
+The plain per-group FP64 path is timed on the same input for the speed-up,
+the oracle on a bounded sample of the same groups on the host cores.
+
+Prints one JSON line.  Only the cpu_baseline leg imports the oracle.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-updates/s at 256^3 CTU+PPM+HLLC vs plain; HBM roofline %; p50/p99 step"
+# Algorithmic floating-point operations per cell update of CTU + PPM(char) +
+# HLLC, counted by the op-counting build of the oracle on a periodic box
+# (no ghost-ring recomputation): + - * / sqrt and comparisons = 1, sign ops
+# free.  Regenerate with oracle/count_ops.py.
+OPS_PER_CELL = 2693.9
+# Non-packed FP32 VALU peak: 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz.
+ALU_PEAK = 256 * 64 * 2 * 2.4e9
+HBM_PEAK = 8.0e12
+# Algorithmic HBM bytes per cell update of the solver kernel (FP32): read the
+# ghosted input (22^3 / 16^3 cells x 5 x 4 B) and write the interior (5 x 4 B).
+BYTES_PER_CELL = (22 ** 3 / 16 ** 3) * 20.0 + 20.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=50)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--n", type=int, default=256, help="box size (multiple of 16)")
+    p.add_argument("--plain-steps", type=int, default=2)
+    p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-plain", action="store_true")
+    p.add_argument("--no-autotune", action="store_true", help="skip the launch-shape autotuner")
+    p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                   help="only run a device-to-device copy of MIB MiB three times (HBM counter calibration)")
+    return p.parse_args()
+
+
+def traffic_from_profile(kernel_src_hash: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "ctu_ppm_hllc_256_counters.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.strip().startswith("- "):
+            k, v = line.strip()[2:].split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_src_hash:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("fused_ctu.hpp", "hydro_math.hpp", "fused_ctu_f32.hip"):
+        with open(os.path.join(ROOT, "paper_1103_3373_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def cpu_baseline(ghosted_dev, dt: float, dh: float, gamma: float, budget_s: float):
+    """The FP64 oracle, single-threaded, on the leading groups of the same
+    ghosted input (copied to the host 32 groups at a time) until the time
+    budget is used."""
+    import oracle as O
+    O._lib()
+    total = ghosted_dev.shape[0]
+    t0 = time.perf_counter()
+    done = 0
+    el = 0.0
+    while done < total and el < budget_s:
+        chunk = ghosted_dev[done:done + 32].cpu().numpy().astype(np.float64)
+        for q in range(chunk.shape[0]):
+            t1 = time.perf_counter()
+            O.solve_groups(chunk[q:q + 1], 3, dt, dh, gamma, O.CTU, O.PPM, O.HLLC, O.VANLEER, O.F_CHAR)
+            el += time.perf_counter() - t1
+            done += 1
+            if el >= budget_s:
+                break
+    return {"value": done * 4096 / el, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} of {total} patch groups of the same first-step input (CTU+PPM(char)+HLLC), "
+                      f"FP64 oracle (g++ -O2), one thread, {el:.1f} s of oracle time"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU runs are not part of "
+              "this build.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1103_3373_amd import hydro as H
+    from paper_1103_3373_amd import workloads as W
+
+    if args.copy_calibration:
+        nb = args.copy_calibration << 20
+        a = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nb, "copy_bytes_written": nb, "launches": 3}))
+        return
+
+    n = args.n
+    gamma, dh, cfl = 1.4, 1.0 / n, 0.5
+    G = (n // 16) ** 3
+    cells = n ** 3
+    dev = torch.device("cuda")
+    print(f"[bench] generating {n}^3 lognormal+blast input", file=sys.stderr, flush=True)
+    box = W.lognormal_blast_box(n, gamma=gamma, seed=W.IC_SEED)
+    state = torch.from_numpy(W.box_to_groups(box).astype(np.float32)).to(dev)
+    nxt = torch.empty_like(state)
+    g = H.ghost_width(H.CTU, H.PPM)
+    ghosted = torch.empty((G, 5, 16 + 2 * g, 16 + 2 * g, 16 + 2 * g), dtype=torch.float32, device=dev)
+    dt_dev = torch.empty(1, dtype=torch.float64, device=dev)
+    sums = torch.empty(5, dtype=torch.float64, device=dev)
+    spec = H.make_spec(H.CTU, H.PPM, H.HLLC, H.VANLEER, gamma=gamma, char=True)
+    tuned = None
+    if not args.no_autotune:
+        tuned = H.autotune(spec, G)
+        print(f"[bench] autotune: grid {tuned}", file=sys.stderr, flush=True)
+    # Segment tables for both buffer orientations (state <-> nxt ping-pong).
+    segA = H.seg_table([(ghosted, nxt, None, dt_dev, 1.0, dh, 0, G)], dev)
+    segB = H.seg_table([(ghosted, state, None, dt_dev, 1.0, dh, 0, G)], dev)
+    stream = torch.cuda.current_stream()
+
+    H.cfl_dt(state, dh, gamma, cfl, dt_out=dt_dev)
+    torch.cuda.synchronize()
+    dt0 = dt_dev.item()
+
+    k_ev = []  # (start, end) events around every solver launch in the timed region
+
+    def step(i, record):
+        src, dst, seg = (state, nxt, segA) if i % 2 == 0 else (nxt, state, segB)
+        H.fill_ghosts_periodic(src, g, ghosted, grouped=True, shape=(n, n, n))
+        if record:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+        H.solve_batch(seg, 1, G, spec)
+        if record:
+            e1.record(stream)
+            k_ev.append((e0, e1))
+        H.cfl_dt(dst, dh, gamma, cfl, dt_out=dt_dev)
+        H.conserved_sums(dst, dh, sums_out=sums)
+
+    print(f"[bench] warmup {args.warmup} steps", file=sys.stderr, flush=True)
+    for i in range(args.warmup):
+        step(i, False)
+    torch.cuda.synchronize()
+    step_ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step_ev[0].record(stream)
+    for i in range(args.steps):
+        step(args.warmup + i, True)
+        step_ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per_step = np.array([step_ev[i].elapsed_time(step_ev[i + 1]) for i in range(args.steps)])  # ms
+    total_ms = step_ev[0].elapsed_time(step_ev[-1])
+    kern_ms = np.array([a.elapsed_time(b) for a, b in k_ev])
+    ms_per_step = total_ms / args.steps
+    value = cells / (ms_per_step * 1e-3)
+    kern_avg = float(kern_ms.mean())
+    achieved = OPS_PER_CELL * cells / (kern_avg * 1e-3)
+    final_dt = dt_dev.item()
+    final_sums = sums.cpu().numpy().tolist()
+    assert np.isfinite(final_dt) and final_dt > 0, final_dt
+
+    # Plain per-group FP64 path on the same first-step input (solver only).
+    plain = None
+    if not args.no_plain and args.plain_steps > 0:
+        print(f"[bench] plain FP64 path, {args.plain_steps} launches", file=sys.stderr, flush=True)
+        st64 = torch.from_numpy(W.box_to_groups(box)).to(dev)
+        gh64 = H.fill_ghosts_periodic(st64, g, grouped=True, shape=(n, n, n))
+        del st64
+        out64 = torch.empty((G, 5, 16, 16, 16), dtype=torch.float64, device=dev)
+        H.solve_groups(gh64, out64, None, dt=dt0, dh=dh, gamma=gamma, scheme=H.CTU, recon=H.PPM, riemann=H.HLLC,
+                       limiter=H.VANLEER, char=True, plain=True)
+        torch.cuda.synchronize()
+        pe = [torch.cuda.Event(enable_timing=True) for _ in range(args.plain_steps + 1)]
+        pe[0].record(stream)
+        for i in range(args.plain_steps):
+            H.solve_groups(gh64, out64, None, dt=dt0, dh=dh, gamma=gamma, scheme=H.CTU, recon=H.PPM,
+                           riemann=H.HLLC, limiter=H.VANLEER, char=True, plain=True)
+            pe[i + 1].record(stream)
+        torch.cuda.synchronize()
+        pms = pe[0].elapsed_time(pe[-1]) / args.plain_steps
+        plain = {"path": "plain per-group FP64 (one workgroup per group, global temporaries)",
+                 "ms_per_solve": round(pms, 3), "cell_updates_per_s": cells / (pms * 1e-3),
+                 "speedup_of_fused_solve": round(pms / kern_avg, 2)}
+        del gh64, out64
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] oracle CPU baseline", file=sys.stderr, flush=True)
+        H.fill_ghosts_periodic(state, g, ghosted, grouped=True, shape=(n, n, n))
+        torch.cuda.synchronize()
+        cpu = cpu_baseline(ghosted, dt0, dh, gamma, args.cpu_seconds)
+
+    src_hash = kernel_source_hash()
+    traffic = traffic_from_profile(src_hash)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded lognormal density, Mach-1 smooth velocities, 4 blasts p=100 r=8)",
+        "config": {"workload": f"{n}^3 periodic box, {G} patch groups of 16^3 + 3 ghost cells, CTU+PPM(char, van "
+                               f"Leer)+HLLC, gamma 1.4, CFL 0.5", "n_groups": G, "ghost": g,
+                   "step": "ghost fill + fused batched solve + FP64 dt + FP64 sums"},
+        "p50_step_ms": float(np.percentile(per_step, 50)),
+        "p99_step_ms": float(np.percentile(per_step, 99)),
+        "wall_s": wall,
+        "solver_kernel_ms": kern_avg,
+        "solver_cell_updates_per_s": cells / (kern_avg * 1e-3),
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / ALU_PEAK, "traffic": traffic,
+                     "ops_per_cell": OPS_PER_CELL, "kernel": "ctu_fused_kernel<float, PPM, HLLC>",
+                     "kernel_source_sha256": src_hash},
+        "hbm": {"algorithmic_bytes_per_cell": BYTES_PER_CELL,
+                "algorithmic_GBps": BYTES_PER_CELL * cells / (kern_avg * 1e-3) / 1e9,
+                "frac_of_8TBps": BYTES_PER_CELL * cells / (kern_avg * 1e-3) / HBM_PEAK},
+        "plain": plain,
+        "cpu_baseline": cpu,
+        "autotune_grid": tuned,
+        "final_dt": final_dt,
+        "final_sums": final_sums,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -127,7 +127,13 @@ int check_options(int scheme, int recon, int riemann, int limiter, int flags) {
 }
 
 // ---- launch-shape cache (autotuner) ----------------------------------------
-std::map<std::string, int> g_tune;
+// A launch shape is the persistent grid size and the register-budget variant
+// (minimum waves per SIMD) of the fused kernel.
+struct Tune {
+  int grid;   // 0 = default (one resident wave of workgroups)
+  int waves;  // 2 or 4
+};
+std::map<std::string, Tune> g_tune;
 bool g_tune_loaded = false;
 
 std::string tune_key(int f64, int scheme, int recon, int riemann, int charlim) {
@@ -143,33 +149,32 @@ void tune_load() {
   FILE* f = fopen(path, "r");
   if (!f) return;
   char key[128];
-  int v;
-  while (fscanf(f, "%127s %d", key, &v) == 2) g_tune[key] = v;
+  int gr, wv;
+  while (fscanf(f, "%127s %d %d", key, &gr, &wv) == 3) g_tune[key] = Tune{gr, wv};
   fclose(f);
 }
-int default_grid(long long n_groups) {
-  // Persistent launch: a fixed multiple of the CU count, never more than the
-  // number of groups.
+int cu_count() {
   int cus = 256;
   hipDeviceProp_t prop;
   int dev;
   if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
     cus = prop.multiProcessorCount;
-  long long g = (long long)cus * 4;
-  if (g > n_groups) g = n_groups;
-  return (int)(g < 1 ? 1 : g);
+  return cus;
 }
-int tuned_grid(int f64, int scheme, int recon, int riemann, int charlim, long long n_groups) {
+Tune tuned(int f64, int scheme, int recon, int riemann, int charlim, long long n_groups) {
   tune_load();
   auto it = g_tune.find(tune_key(f64, scheme, recon, riemann, charlim));
-  int g = (it != g_tune.end()) ? it->second : default_grid(n_groups);
-  if (g > n_groups) g = (int)n_groups;
-  return g < 1 ? 1 : g;
+  Tune t = (it != g_tune.end()) ? it->second : Tune{0, 2};
+  if (f64) t.waves = 2;
+  if (t.grid <= 0) t.grid = cu_count() * (t.waves == 4 ? 2 : 1);
+  if (t.grid > n_groups) t.grid = (int)n_groups;
+  if (t.grid < 1) t.grid = 1;
+  return t;
 }
 
 template <typename T>
 int run_fused(const hy::Seg* segs_dev, int n_segs, long long n_groups, int g, int scheme, int recon, int riemann,
-              int limiter, int flags, double gamma, unsigned long long* diag, int grid, hipStream_t st,
+              int limiter, int flags, double gamma, unsigned long long* diag, int grid, int waves, hipStream_t st,
               const hy::Seg* seg0 = nullptr, double dt0 = 0.0) {
   hy::FusedArgs<T> a;
   a.segs = segs_dev;
@@ -189,6 +194,7 @@ int run_fused(const hy::Seg* segs_dev, int n_segs, long long n_groups, int g, in
   a.dt0 = dt0;
   hy::FusedCfg cfg;
   cfg.grid = grid;
+  cfg.waves = waves;
   hipError_t e = hy::launch_fused(a, scheme, recon, riemann, cfg, st);
   if (e != hipSuccess) return hip_fail(e, "fused solver launch");
   return 0;
@@ -251,12 +257,12 @@ int hydro_solve_groups(const void* in, void* out, void* flux_out, int n_groups, 
   }
   // Fused path: a single segment passed by value, host dt included.
   hy::Seg seg{in, out, flux_out, nullptr, 1.0, dh, 0, n_groups};
-  const int grid = tuned_grid(f64, scheme, reconstruction, riemann, (flags & HYDRO_CHAR) ? 1 : 0, n_groups);
+  const Tune tu = tuned(f64, scheme, reconstruction, riemann, (flags & HYDRO_CHAR) ? 1 : 0, n_groups);
   if (f64)
     return run_fused<double>(nullptr, 1, n_groups, g, scheme, reconstruction, riemann, limiter, flags, gamma,
-                             ds->diag, grid, st, &seg, dt);
+                             ds->diag, tu.grid, tu.waves, st, &seg, dt);
   return run_fused<float>(nullptr, 1, n_groups, g, scheme, reconstruction, riemann, limiter, flags, gamma, ds->diag,
-                          grid, st, &seg, dt);
+                          tu.grid, tu.waves, st, &seg, dt);
 }
 
 int hydro_solve_batch(const struct hydro_seg* segs, int n_segs, long long n_groups_total,
@@ -278,14 +284,14 @@ int hydro_solve_batch(const struct hydro_seg* segs, int n_segs, long long n_grou
   if (int rc = device_state(&ds)) return rc;
   const bool f64 = (spec->flags & HYDRO_F64) != 0;
   const int g = ghost_width(spec->scheme, spec->reconstruction);
-  const int grid = tuned_grid(f64, spec->scheme, spec->reconstruction, spec->riemann, charlim, n_groups_total);
+  const Tune tu = tuned(f64, spec->scheme, spec->reconstruction, spec->riemann, charlim, n_groups_total);
   const hy::Seg* sd = (const hy::Seg*)segs;
   hipStream_t st = (hipStream_t)stream;
   if (f64)
     return run_fused<double>(sd, n_segs, n_groups_total, g, spec->scheme, spec->reconstruction, spec->riemann,
-                             spec->limiter, spec->flags, spec->gamma, ds->diag, grid, st);
+                             spec->limiter, spec->flags, spec->gamma, ds->diag, tu.grid, tu.waves, st);
   return run_fused<float>(sd, n_segs, n_groups_total, g, spec->scheme, spec->reconstruction, spec->riemann,
-                          spec->limiter, spec->flags, spec->gamma, ds->diag, grid, st);
+                          spec->limiter, spec->flags, spec->gamma, ds->diag, tu.grid, tu.waves, st);
 }
 
 int hydro_cfl_dt(const void* U, int n_groups, double dh, double gamma, double cfl, int flags, double* dt_out,
@@ -435,60 +441,59 @@ int hydro_autotune(const struct hydro_spec* spec, int n_groups_hint, void* strea
     if (e == hipSuccess) e = hipMemcpyAsync(sd, &s, sizeof(s), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
   }
-  int cus = 256;
-  {
-    hipDeviceProp_t prop;
-    int dev;
-    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-      cus = prop.multiProcessorCount;
-  }
+  const int cus = cu_count();
   DeviceState* ds = nullptr;
   {
     std::lock_guard<std::mutex> lock(g_mu);
     if (int rc = device_state(&ds)) { hipFree(in); hipFree(out); hipFree(dtd); hipFree(sd); return rc; }
   }
-  const int mults[] = {1, 2, 3, 4, 6, 8, 12, 16};
-  int best = -1;
+  // Candidates: register variant x persistent grid (multiples of the CU count).
+  const int mults[] = {1, 2, 3, 4, 6, 8};
+  const int variants[] = {2, 4};
+  Tune best{-1, 2};
   float best_ms = 1e30f;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
-  for (int m : mults) {
-    if (e != hipSuccess) break;
-    long long grid = (long long)cus * m;
-    if (grid > n) grid = n;
-    float ms_min = 1e30f;
-    for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
-      e = hipEventRecord(e0, st);
-      int rc = f64 ? run_fused<double>(sd, 1, n, g, spec->scheme, spec->reconstruction, spec->riemann, spec->limiter,
-                                       spec->flags, spec->gamma, ds->diag, (int)grid, st)
-                   : run_fused<float>(sd, 1, n, g, spec->scheme, spec->reconstruction, spec->riemann, spec->limiter,
-                                      spec->flags, spec->gamma, ds->diag, (int)grid, st);
-      if (rc) { e = hipErrorLaunchFailure; break; }
-      if (e == hipSuccess) e = hipEventRecord(e1, st);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      float ms = 0;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (rep > 0 && ms < ms_min) ms_min = ms;  // first launch is a warm-up
+  for (int wv : variants) {
+    if (f64 && wv != 2) continue;
+    for (int m : mults) {
+      if (e != hipSuccess) break;
+      long long grid = (long long)cus * m;
+      if (grid > n) grid = n;
+      float ms_min = 1e30f;
+      for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+        e = hipEventRecord(e0, st);
+        int rc = f64 ? run_fused<double>(sd, 1, n, g, spec->scheme, spec->reconstruction, spec->riemann,
+                                         spec->limiter, spec->flags, spec->gamma, ds->diag, (int)grid, wv, st)
+                     : run_fused<float>(sd, 1, n, g, spec->scheme, spec->reconstruction, spec->riemann,
+                                        spec->limiter, spec->flags, spec->gamma, ds->diag, (int)grid, wv, st);
+        if (rc) { e = hipErrorLaunchFailure; break; }
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (rep > 0 && ms < ms_min) ms_min = ms;  // the first launch is a warm-up
+      }
+      if (ms_min < best_ms) { best_ms = ms_min; best = Tune{(int)grid, wv}; }
+      if (grid == n) break;
     }
-    if (ms_min < best_ms) { best_ms = ms_min; best = (int)grid; }
-    if (grid == n) break;
   }
   if (e0) hipEventDestroy(e0);
   if (e1) hipEventDestroy(e1);
   hipFree(in); hipFree(out); hipFree(dtd); hipFree(sd);
-  if (e != hipSuccess || best < 0) return hip_fail(e == hipSuccess ? hipErrorUnknown : e, "autotune");
+  if (e != hipSuccess || best.grid < 0) return hip_fail(e == hipSuccess ? hipErrorUnknown : e, "autotune");
   std::lock_guard<std::mutex> lock(g_mu);
   tune_load();
   const std::string key = tune_key(f64, spec->scheme, spec->reconstruction, spec->riemann, charlim);
   g_tune[key] = best;
   if (const char* path = getenv("HYDRO_TUNE_CACHE")) {
     if (FILE* f = fopen(path, "a")) {
-      fprintf(f, "%s %d\n", key.c_str(), best);
+      fprintf(f, "%s %d %d\n", key.c_str(), best.grid, best.waves);
       fclose(f);
     }
   }
-  return best;
+  return best.grid;
 }
 
 void hydro_shutdown(void) {

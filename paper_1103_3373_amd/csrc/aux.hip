@@ -16,32 +16,35 @@ namespace hy {
 // [G][5][16][16][16] (grouped != 0).  One thread per output cell, x fastest.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(256) fill_periodic_kernel(const T* __restrict__ box, int nx, int ny, int nz, int g,
-                                                            int grouped, T* __restrict__ out, long long total) {
+__global__ void __launch_bounds__(512) fill_periodic_kernel(const T* __restrict__ box, int nx, int ny, int nz, int g,
+                                                            int grouped, T* __restrict__ out, long long g_off) {
+  // blockIdx.x = plane k of the padded group, blockIdx.y = group; threads
+  // cover the N x N plane, x fastest (coalesced writes).
   const int N = 16 + 2 * g;
   const long long nc = (long long)N * N * N;
+  const int k = blockIdx.x;
+  const long long G = g_off + blockIdx.y;
   const int ngx = nx >> 4, ngy = ny >> 4;
   const long long boxc = (long long)nx * ny * nz;
-  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
-       t += (long long)gridDim.x * blockDim.x) {
-    const long long G = t / nc;
-    const int r = (int)(t - G * nc);
-    const int i = r % N, j = (r / N) % N, k = r / (N * N);
-    const int gx = (int)(G % ngx), gy = (int)((G / ngx) % ngy), gz = (int)(G / ((long long)ngx * ngy));
-    int sx = gx * 16 + i - g, sy = gy * 16 + j - g, sz = gz * 16 + k - g;
+  const int gx = (int)(G % ngx), gy = (int)((G / ngx) % ngy), gz = (int)(G / ((long long)ngx * ngy));
+  int sz = gz * 16 + k - g;
+  sz += (sz < 0) ? nz : 0;
+  sz -= (sz >= nz) ? nz : 0;
+  T* o = out + G * 5 * nc + (long long)k * N * N;
+  for (int r = threadIdx.x; r < N * N; r += blockDim.x) {
+    const int i = r % N, j = r / N;
+    int sx = gx * 16 + i - g, sy = gy * 16 + j - g;
     sx += (sx < 0) ? nx : 0; sx -= (sx >= nx) ? nx : 0;
     sy += (sy < 0) ? ny : 0; sy -= (sy >= ny) ? ny : 0;
-    sz += (sz < 0) ? nz : 0; sz -= (sz >= nz) ? nz : 0;
-    T* o = out + G * 5 * nc + r;
     if (grouped) {
       const long long sg = ((long long)(sz >> 4) * ngy + (sy >> 4)) * ngx + (sx >> 4);
       const T* s = box + sg * 5 * 4096 + (((sz & 15) * 16 + (sy & 15)) * 16 + (sx & 15));
 #pragma unroll
-      for (int n = 0; n < 5; ++n) o[n * nc] = s[n * 4096];
+      for (int n = 0; n < 5; ++n) o[n * nc + r] = s[n * 4096];
     } else {
       const T* s = box + ((long long)sz * ny + sy) * nx + sx;
 #pragma unroll
-      for (int n = 0; n < 5; ++n) o[n * nc] = s[n * boxc];
+      for (int n = 0; n < 5; ++n) o[n * nc + r] = s[n * boxc];
     }
   }
 }
@@ -49,12 +52,16 @@ __global__ void __launch_bounds__(256) fill_periodic_kernel(const T* __restrict_
 template <typename T>
 hipError_t launch_fill_periodic(const T* box, int nx, int ny, int nz, int g, int grouped, T* out, hipStream_t st) {
   const int N = 16 + 2 * g;
-  const long long total = (long long)(nx / 16) * (ny / 16) * (nz / 16) * N * N * N;
-  if (total == 0) return hipSuccess;
-  long long blocks = (total + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
-  fill_periodic_kernel<T><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(box, nx, ny, nz, g, grouped, out, total);
-  return hipGetLastError();
+  const long long groups = (long long)(nx / 16) * (ny / 16) * (nz / 16);
+  if (groups == 0) return hipSuccess;
+  // grid.y is limited to 65535 groups per launch.
+  for (long long g0 = 0; g0 < groups; g0 += 65535) {
+    const long long cnt = groups - g0 < 65535 ? groups - g0 : 65535;
+    fill_periodic_kernel<T><<<dim3(N, (unsigned)cnt), dim3(512), 0, st>>>(box, nx, ny, nz, g, grouped, out, g0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 template hipError_t launch_fill_periodic<float>(const float*, int, int, int, int, int, float*, hipStream_t);
 template hipError_t launch_fill_periodic<double>(const double*, int, int, int, int, int, double*, hipStream_t);
@@ -140,32 +147,28 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// U: n_blocks blocks of [5][4096]; one partial max per workgroup.  The
+// per-cell expression is written out in a fixed order with contraction off.
 template <typename T>
-__device__ __attribute__((noinline)) double cell_signal_speed(const T* u, long long cells, double gamma) {
+__global__ void __launch_bounds__(256) maxspeed_kernel(const T* __restrict__ U, long long n_blocks, double gamma,
+                                                       double* __restrict__ partial) {
 #pragma clang fp contract(off)
-  const double rho = (double)u[0];
-  const double mx = (double)u[cells], my = (double)u[2 * cells], mz = (double)u[3 * cells];
-  const double vx = mx / rho, vy = my / rho, vz = mz / rho;
-  const double ke = 0.5 * (mx * vx + my * vy + mz * vz);
-  const double p = (gamma - 1.0) * ((double)u[4 * cells] - ke);
-  const double cs = __builtin_sqrt(gamma * p / rho);
-  double av = __builtin_fabs(vx);
-  if (__builtin_fabs(vy) > av) av = __builtin_fabs(vy);
-  if (__builtin_fabs(vz) > av) av = __builtin_fabs(vz);
-  return av + cs;
-}
-
-// U: n_blocks blocks of [5][cells]; one partial max per workgroup.
-template <typename T>
-__global__ void __launch_bounds__(256) maxspeed_kernel(const T* __restrict__ U, long long n_blocks, long long cells,
-                                                       double gamma, double* __restrict__ partial) {
   __shared__ double red[4];
   double m = 0.0;
-  const long long total = n_blocks * cells;
+  const long long total = n_blocks << 12;
   for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
        t += (long long)gridDim.x * blockDim.x) {
-    const long long b = t / cells, q = t - b * cells;
-    const double s = cell_signal_speed(U + b * 5 * cells + q, cells, gamma);
+    const T* u = U + ((t >> 12) * 5 << 12) + (t & 4095);
+    const double rho = (double)u[0];
+    const double mx = (double)u[4096], my = (double)u[2 * 4096], mz = (double)u[3 * 4096];
+    const double vx = mx / rho, vy = my / rho, vz = mz / rho;
+    const double ke = 0.5 * (mx * vx + my * vy + mz * vz);
+    const double p = (gamma - 1.0) * ((double)u[4 * 4096] - ke);
+    const double cs = __builtin_sqrt(gamma * p / rho);
+    double av = __builtin_fabs(vx);
+    if (__builtin_fabs(vy) > av) av = __builtin_fabs(vy);
+    if (__builtin_fabs(vz) > av) av = __builtin_fabs(vz);
+    const double s = av + cs;
     m = s > m ? s : m;
   }
   m = wave_max(m);
@@ -192,7 +195,8 @@ __global__ void __launch_bounds__(256) dt_finish_kernel(const double* __restrict
 template <typename T>
 hipError_t launch_maxspeed(const T* U, long long n_blocks, long long cells, double gamma, double* partial,
                            int n_partial, hipStream_t st) {
-  maxspeed_kernel<T><<<dim3(n_partial), dim3(256), 0, st>>>(U, n_blocks, cells, gamma, partial);
+  if (cells != 4096) return hipErrorInvalidValue;
+  maxspeed_kernel<T><<<dim3(n_partial), dim3(256), 0, st>>>(U, n_blocks, gamma, partial);
   return hipGetLastError();
 }
 template hipError_t launch_maxspeed<float>(const float*, long long, long long, double, double*, int, hipStream_t);
@@ -211,18 +215,17 @@ hipError_t launch_dt_finish(const double* partial, int n_partial, double dh, dou
 // timing, so repeated calls are bitwise identical.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(256) sums_kernel(const T* __restrict__ U, long long n_blocks, long long cells,
+__global__ void __launch_bounds__(256) sums_kernel(const T* __restrict__ U, long long n_blocks,
                                                    double* __restrict__ partial) {
   __shared__ double red[5][4];
-  const long long total = n_blocks * cells;
+  const long long total = n_blocks << 12;
   const long long per = (total + gridDim.x - 1) / gridDim.x;
   const long long lo = blockIdx.x * per, hi = min(total, lo + per);
   double s[5] = {0, 0, 0, 0, 0};
   for (long long t = lo + threadIdx.x; t < hi; t += blockDim.x) {
-    const long long b = t / cells, q = t - b * cells;
-    const T* u = U + b * 5 * cells + q;
+    const T* u = U + ((t >> 12) * 5 << 12) + (t & 4095);
 #pragma unroll
-    for (int n = 0; n < 5; ++n) s[n] += (double)u[n * cells];
+    for (int n = 0; n < 5; ++n) s[n] += (double)u[n * 4096];
   }
 #pragma unroll
   for (int n = 0; n < 5; ++n) {
@@ -248,7 +251,8 @@ __global__ void __launch_bounds__(64) sums_finish_kernel(const double* __restric
 template <typename T>
 hipError_t launch_sums(const T* U, long long n_blocks, long long cells, double dh, double* partial, int n_partial,
                        double* sums_out, hipStream_t st) {
-  sums_kernel<T><<<dim3(n_partial), dim3(256), 0, st>>>(U, n_blocks, cells, partial);
+  if (cells != 4096) return hipErrorInvalidValue;
+  sums_kernel<T><<<dim3(n_partial), dim3(256), 0, st>>>(U, n_blocks, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   sums_finish_kernel<<<dim3(1), dim3(64), 0, st>>>(partial, n_partial, dh * dh * dh, sums_out);

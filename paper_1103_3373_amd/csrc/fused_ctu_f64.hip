@@ -1,0 +1,36 @@
+// Instantiations of the fused CTU kernel for double.
+#include "fused_ctu.hpp"
+
+namespace hy {
+
+template <bool PPM, int RS, int WAVES>
+static hipError_t launch_one(const FusedArgs<double>& a, int grid, hipStream_t st) {
+  auto k = ctu::ctu_fused_kernel<double, PPM, RS, WAVES>;
+  const size_t shm = (size_t)ctu::kLds * sizeof(double);
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  k<<<dim3(grid), dim3(ctu::kThreads), shm, st>>>(a);
+  return hipGetLastError();
+}
+
+template <int WAVES>
+static hipError_t launch_w(const FusedArgs<double>& a, int recon, int riemann, int grid, hipStream_t st) {
+  if (recon == 1) {
+    if (riemann == 0) return launch_one<true, 0, WAVES>(a, grid, st);
+    if (riemann == 1) return launch_one<true, 1, WAVES>(a, grid, st);
+    return launch_one<true, 2, WAVES>(a, grid, st);
+  }
+  if (riemann == 0) return launch_one<false, 0, WAVES>(a, grid, st);
+  if (riemann == 1) return launch_one<false, 1, WAVES>(a, grid, st);
+  return launch_one<false, 2, WAVES>(a, grid, st);
+}
+
+hipError_t launch_ctu_f64(const FusedArgs<double>& a, int recon, int riemann, const FusedCfg& cfg, hipStream_t st) {
+  return launch_w<2>(a, recon, riemann, cfg.grid, st);
+}
+
+}  // namespace hy

@@ -56,6 +56,7 @@ struct FusedArgs {
 
 struct FusedCfg {
   int grid;          // number of workgroups (persistent)
+  int waves;         // register budget variant: minimum waves per SIMD (2 or 4)
 };
 
 bool fused_supported(int scheme, int recon, int riemann, int charlim);

@@ -36,13 +36,23 @@ struct Phys {
 };
 
 // ---- scalar helpers ---------------------------------------------------------
-template <typename T> HY_DEV T vmin(T a, T b) { return a < b ? a : b; }
-template <typename T> HY_DEV T vmax(T a, T b) { return a > b ? a : b; }
+// min / max map to single v_min / v_max instructions (operands are never NaN).
+HY_DEV float vmin(float a, float b) { return __builtin_fminf(a, b); }
+HY_DEV double vmin(double a, double b) { return __builtin_fmin(a, b); }
+HY_DEV float vmax(float a, float b) { return __builtin_fmaxf(a, b); }
+HY_DEV double vmax(double a, double b) { return __builtin_fmax(a, b); }
+HY_DEV float vsign_of(float m, float s) { return __builtin_copysignf(m, s); }
+HY_DEV double vsign_of(double m, double s) { return __builtin_copysign(m, s); }
 HY_DEV float vabs(float a) { return __builtin_fabsf(a); }
 HY_DEV double vabs(double a) { return __builtin_fabs(a); }
-HY_DEV float vsqrt(float a) { return __builtin_sqrtf(a); }
+// FP32 uses the hardware reciprocal and square root (about 1 ulp) instead
+// of the multi-instruction correctly rounded sequences; FP64 stays IEEE.
+HY_DEV float vsqrt(float a) { return __builtin_amdgcn_sqrtf(a); }
 HY_DEV double vsqrt(double a) { return __builtin_sqrt(a); }
-template <typename T> HY_DEV T vrcp(T a) { return T(1) / a; }
+HY_DEV float vrcp(float a) { return __builtin_amdgcn_rcpf(a); }
+HY_DEV double vrcp(double a) { return 1.0 / a; }
+HY_DEV float vdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+HY_DEV double vdiv(double a, double b) { return a / b; }
 
 // ---- frames -----------------------------------------------------------------
 template <int D> struct Frame {
@@ -114,15 +124,15 @@ template <typename T> HY_DEV T limit(T dl, T dr, const Phys<T>& ph) {
   switch (ph.limiter) {
     case 0: {
       T m = vmin(vmin(ph.theta * vabs(dl), ph.theta * vabs(dr)), vabs(dc));
-      r = dc > T(0) ? m : -m;
+      r = vsign_of(m, dc);  // dc != 0 because dl and dr share a sign
       break;
     }
-    case 1: r = T(2) * prod / (dl + dr); break;
-    case 2: r = prod * (dl + dr) / (dl * dl + dr * dr); break;
+    case 1: r = vdiv(T(2) * prod, dl + dr); break;
+    case 2: r = vdiv(prod * (dl + dr), dl * dl + dr * dr); break;
     default: {
-      T vl = vabs(T(2) * prod / (dl + dr));
+      T vl = vabs(vdiv(T(2) * prod, dl + dr));
       T m = vmin(vmin(vmin(ph.theta * vabs(dl), ph.theta * vabs(dr)), vabs(dc)), vl);
-      r = dc > T(0) ? m : -m;
+      r = vsign_of(m, dc);
       break;
     }
   }
@@ -301,7 +311,7 @@ template <typename T> HY_DEV Roe<T> roe_avg(const V5<T>& L, const V5<T>& R, T EL
   a.v = wl * L[2] + wr * R[2];
   a.w = wl * L[3] + wr * R[3];
   // H = (E + p) / rho; sqrt(rho) * H = (E + p) / sqrt(rho)
-  a.H = ((EL + L[4]) / sL + (ER + R[4]) / sR) * inv;
+  a.H = (vdiv(EL + L[4], sL) + vdiv(ER + R[4], sR)) * inv;
   a.c2 = ph.gm1 * (a.H - T(0.5) * (a.u * a.u + a.v * a.v + a.w * a.w));
   return a;
 }
@@ -340,7 +350,7 @@ HY_DEV V5<T> hllc(const V5<T>& L, const V5<T>& R, const Phys<T>& ph) {
   T SR = vmax(R[1] + cR, a.u + ct);
   T mL = L[0] * (SL - L[1]);
   T mR = R[0] * (SR - R[1]);
-  T Ss = (R[4] - L[4] + mL * L[1] - mR * R[1]) / (mL - mR);
+  T Ss = vdiv(R[4] - L[4] + mL * L[1] - mR * R[1], mL - mR);
   // Select the side, then form its star flux; supersonic cases reduce to
   // the upwind physical flux.
   bool supL = SL >= T(0), supR = SR <= T(0);
@@ -351,7 +361,7 @@ HY_DEV V5<T> hllc(const V5<T>& L, const V5<T>& R, const Phys<T>& ph) {
   T m = left ? mL : mR;
   V5<T> F = flux_of(W, ph);
   if (supL || supR) return F;
-  T fac = m / (S - Ss);
+  T fac = vdiv(m, S - Ss);
   V5<T> U;
   U[0] = W[0]; U[1] = W[0] * W[1]; U[2] = W[0] * W[2]; U[3] = W[0] * W[3]; U[4] = E;
   V5<T> Us;
@@ -359,7 +369,7 @@ HY_DEV V5<T> hllc(const V5<T>& L, const V5<T>& R, const Phys<T>& ph) {
   Us[1] = fac * Ss;
   Us[2] = fac * W[2];
   Us[3] = fac * W[3];
-  Us[4] = fac * (E / W[0] + (Ss - W[1]) * (Ss + W[4] / m));
+  Us[4] = fac * (vdiv(E, W[0]) + (Ss - W[1]) * (Ss + vdiv(W[4], m)));
   V5<T> Fs;
 #pragma unroll
   for (int n = 0; n < 5; ++n) Fs[n] = F[n] + S * (Us[n] - U[n]);
@@ -396,13 +406,13 @@ HY_DEV V5<T> roe(const V5<T>& L, const V5<T>& R, const Phys<T>& ph, int* fails) 
     T m1a = L[0] * L[2] + a1 * a.v;
     T m1b = L[0] * L[3] + a1 * a.w;
     T e1 = EL + a1 * (a.H - a.u * ct);
-    T p1 = ph.gm1 * (e1 - T(0.5) * (m1n * m1n + m1a * m1a + m1b * m1b) / r1);
+    T p1 = ph.gm1 * (e1 - vdiv(T(0.5) * (m1n * m1n + m1a * m1a + m1b * m1b), r1));
     T r2 = R[0] - a5;
     T m2n = R[0] * R[1] - a5 * (a.u + ct);
     T m2a = R[0] * R[2] - a5 * a.v;
     T m2b = R[0] * R[3] - a5 * a.w;
     T e2 = ER - a5 * (a.H + a.u * ct);
-    T p2 = ph.gm1 * (e2 - T(0.5) * (m2n * m2n + m2a * m2a + m2b * m2b) / r2);
+    T p2 = ph.gm1 * (e2 - vdiv(T(0.5) * (m2n * m2n + m2a * m2a + m2b * m2b), r2));
     ok = ok && r1 > T(0) && p1 > T(0) && r2 > T(0) && p2 > T(0);
   }
   if (!ok) {

