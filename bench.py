@@ -40,9 +40,10 @@ OPS_PER_CELL = 2693.9
 # Non-packed FP32 VALU peak: 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz.
 ALU_PEAK = 256 * 64 * 2 * 2.4e9
 HBM_PEAK = 8.0e12
-# Algorithmic HBM bytes per cell update of the solver kernel (FP32): read the
-# ghosted input (22^3 / 16^3 cells x 5 x 4 B) and write the interior (5 x 4 B).
-BYTES_PER_CELL = (22 ** 3 / 16 ** 3) * 20.0 + 20.0
+# Algorithmic HBM bytes per cell update of the box solver (FP32): read U^n and
+# write U^{n+1} once each (5 x 4 B each way); ghost cells come from
+# neighbouring groups of the same resident box.
+BYTES_PER_CELL = 40.0
 
 
 def parse():
@@ -56,6 +57,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--no-autotune", action="store_true", help="skip the launch-shape autotuner")
+    p.add_argument("--graph-replays", type=int, default=10, help="replays of a captured two-step HIP graph")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="only run a device-to-device copy of MIB MiB three times (HBM counter calibration)")
     return p.parse_args()
@@ -142,7 +144,6 @@ def main():
     state = torch.from_numpy(W.box_to_groups(box).astype(np.float32)).to(dev)
     nxt = torch.empty_like(state)
     g = H.ghost_width(H.CTU, H.PPM)
-    ghosted = torch.empty((G, 5, 16 + 2 * g, 16 + 2 * g, 16 + 2 * g), dtype=torch.float32, device=dev)
     dt_dev = torch.empty(1, dtype=torch.float64, device=dev)
     sums = torch.empty(5, dtype=torch.float64, device=dev)
     spec = H.make_spec(H.CTU, H.PPM, H.HLLC, H.VANLEER, gamma=gamma, char=True)
@@ -150,10 +151,8 @@ def main():
     if not args.no_autotune:
         tuned = H.autotune(spec, G)
         print(f"[bench] autotune: grid {tuned}", file=sys.stderr, flush=True)
-    # Segment tables for both buffer orientations (state <-> nxt ping-pong).
-    segA = H.seg_table([(ghosted, nxt, None, dt_dev, 1.0, dh, 0, G)], dev)
-    segB = H.seg_table([(ghosted, state, None, dt_dev, 1.0, dh, 0, G)], dev)
     stream = torch.cuda.current_stream()
+    solve_kw = dict(dh=dh, gamma=gamma, scheme=H.CTU, recon=H.PPM, riemann=H.HLLC, limiter=H.VANLEER, char=True)
 
     H.cfl_dt(state, dh, gamma, cfl, dt_out=dt_dev)
     torch.cuda.synchronize()
@@ -162,18 +161,19 @@ def main():
     k_ev = []  # (start, end) events around every solver launch in the timed region
 
     def step(i, record):
-        src, dst, seg = (state, nxt, segA) if i % 2 == 0 else (nxt, state, segB)
-        H.fill_ghosts_periodic(src, g, ghosted, grouped=True, shape=(n, n, n))
+        src, dst = (state, nxt) if i % 2 == 0 else (nxt, state)
         if record:
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-        H.solve_batch(seg, 1, G, spec)
+        # a0 + a1-a8 (+ a11): the fused solver reads the ghost cells from the
+        # resident box and is launched persistently over all groups.
+        H.step_box(src, dst, (n, n, n), dt_dev, **solve_kw)
         if record:
             e1.record(stream)
             k_ev.append((e0, e1))
-        H.cfl_dt(dst, dh, gamma, cfl, dt_out=dt_dev)
-        H.conserved_sums(dst, dh, sums_out=sums)
+        H.cfl_dt(dst, dh, gamma, cfl, dt_out=dt_dev)       # a9
+        H.conserved_sums(dst, dh, sums_out=sums)           # a10
 
     print(f"[bench] warmup {args.warmup} steps", file=sys.stderr, flush=True)
     for i in range(args.warmup):
@@ -190,6 +190,24 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     per_step = np.array([step_ev[i].elapsed_time(step_ev[i + 1]) for i in range(args.steps)])  # ms
+    # The same steps replayed from a captured HIP graph (two steps per graph).
+    graph_ms = None
+    if args.graph_replays > 0:
+        side = torch.cuda.Stream()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=side):
+            step(0, False)
+            step(1, False)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        g0.record(stream)
+        for _ in range(args.graph_replays):
+            graph.replay()
+        g1.record(stream)
+        torch.cuda.synchronize()
+        graph_ms = g0.elapsed_time(g1) / (2 * args.graph_replays)
     total_ms = step_ev[0].elapsed_time(step_ev[-1])
     kern_ms = np.array([a.elapsed_time(b) for a, b in k_ev])
     ms_per_step = total_ms / args.steps
@@ -205,7 +223,7 @@ def main():
     if not args.no_plain and args.plain_steps > 0:
         print(f"[bench] plain FP64 path, {args.plain_steps} launches", file=sys.stderr, flush=True)
         st64 = torch.from_numpy(W.box_to_groups(box)).to(dev)
-        gh64 = H.fill_ghosts_periodic(st64, g, grouped=True, shape=(n, n, n))
+        gh64 = H.fill_ghosts_periodic(st64, g, grouped=True, shape=(n, n, n))  # plain path needs ghosted groups
         del st64
         out64 = torch.empty((G, 5, 16, 16, 16), dtype=torch.float64, device=dev)
         H.solve_groups(gh64, out64, None, dt=dt0, dh=dh, gamma=gamma, scheme=H.CTU, recon=H.PPM, riemann=H.HLLC,
@@ -227,9 +245,12 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] oracle CPU baseline", file=sys.stderr, flush=True)
-        H.fill_ghosts_periodic(state, g, ghosted, grouped=True, shape=(n, n, n))
+        first = torch.from_numpy(W.box_to_groups(box).astype(np.float32)).to(dev)
+        ghosted = H.fill_ghosts_periodic(first, g, grouped=True, shape=(n, n, n))
+        del first
         torch.cuda.synchronize()
         cpu = cpu_baseline(ghosted, dt0, dh, gamma, args.cpu_seconds)
+        del ghosted
 
     src_hash = kernel_source_hash()
     traffic = traffic_from_profile(src_hash)
@@ -248,8 +269,9 @@ def main():
         "data": "synthetic (seeded lognormal density, Mach-1 smooth velocities, 4 blasts p=100 r=8)",
         "config": {"workload": f"{n}^3 periodic box, {G} patch groups of 16^3 + 3 ghost cells, CTU+PPM(char, van "
                                f"Leer)+HLLC, gamma 1.4, CFL 0.5", "n_groups": G, "ghost": g,
-                   "step": "ghost fill + fused batched solve + FP64 dt + FP64 sums"},
+                   "step": "fused box solve (ghosts read from the resident box) + FP64 dt + FP64 sums"},
         "p50_step_ms": float(np.percentile(per_step, 50)),
+        "graph_ms_per_step": graph_ms,
         "p99_step_ms": float(np.percentile(per_step, 99)),
         "wall_s": wall,
         "solver_kernel_ms": kern_avg,

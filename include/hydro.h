@@ -129,10 +129,16 @@ int hydro_fill_ghosts_periodic(const void* box, int nx, int ny, int nz, int g, i
 int hydro_fill_groups_interp(const void* coarse, int cn, const int* layout, int n_groups, int g, double base_dh,
                              int flags, void* groups_out, void* stream);
 
-/* One segment of a batched launch: groups in[count][5][N^3] -> out, flux,
- * advanced by dt = (*dt) * dt_scale with cell size dh.  `dt` points to a
- * device double, so the time step can be produced on the device (e.g. by
- * hydro_cfl_dt) and the launch captured in a graph. */
+/* One segment of a batched launch: `count` groups advanced by
+ * dt = (*dt) * dt_scale with cell size dh.  `dt` points to a device double,
+ * so the time step can be produced on the device (e.g. by hydro_cfl_dt) and
+ * the launch captured in a graph.
+ *   box == 0: in is [count][5][N][N][N] (ghosted groups, N = 16 + 2g).
+ *   box == 1: in is a periodic box stored as groups [count][5][16][16][16],
+ *             count = ngx*ngy*ngz, group index (gz*ngy + gy)*ngx + gx; the
+ *             ghost cells are read from the neighbouring groups (the
+ *             preparation step fused into the solver).  Fused path only.
+ * out is [count][5][16][16][16], flux as for hydro_solve_groups or NULL. */
 struct hydro_seg {
   const void* in;
   void* out;
@@ -142,7 +148,23 @@ struct hydro_seg {
   double dh;
   long long first;     /* global index of the segment's first group */
   long long count;     /* groups in the segment */
+  int ngx, ngy, ngz;   /* box == 1: groups per dimension */
+  int box;
 };
+
+/*
+ * One step of a periodic box held in patch-group order (HYDRO_BOX_GROUPED
+ * layout): box_in, box_out [G][5][16][16][16], G = (nx/16)(ny/16)(nz/16),
+ * with dt read from the device double *dt_dev (times dt_scale).  The ghost
+ * cells are read from the neighbouring groups of box_in, so no ghosted copy
+ * is made (the preparation step of Sec. 4.2 fused into the solver).  nx,
+ * ny, nz positive multiples of 16; box_out must not overlap box_in.
+ * flux_out as for hydro_solve_groups, or NULL.  Fused path only
+ * (HYDRO_EUNSUPPORTED otherwise).
+ */
+int hydro_step_box(const void* box_in, void* box_out, void* flux_out, int nx, int ny, int nz, const double* dt_dev,
+                   double dt_scale, double dh, double gamma, int scheme, int reconstruction, int riemann, int limiter,
+                   int flags, void* stream);
 
 /* Specialization of a batched launch (all segments share it). */
 struct hydro_spec {

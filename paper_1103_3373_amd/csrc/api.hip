@@ -45,14 +45,21 @@ bool overlap(const void* a, size_t na, const void* b, size_t nb) {
   return x < y + nb && y < x + na;
 }
 
-// Library-owned device memory, one set per (device, stream).
+// Library-owned device memory.  The plain path's temporaries are per
+// (device, stream).  Reduction partials come from a per-device pool of slots
+// allocated once, on the first call on that device, so a stream met later
+// (for instance one that is capturing a graph) never allocates.
 struct Workspace {
   void* plain = nullptr;
   size_t plain_bytes = 0;
-  double* partial = nullptr;  // reduction partials
+  double* partial = nullptr;  // reduction partials (a pool slot or own memory)
+  bool own_partial = false;
 };
+const int kPartialSlots = 64;
 struct DeviceState {
   unsigned long long* diag = nullptr;
+  double* partial_pool = nullptr;
+  int partial_used = 0;
   std::map<hipStream_t, Workspace> ws;
 };
 std::mutex g_mu;
@@ -77,6 +84,8 @@ int device_state(DeviceState** out) {
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(diag)");
     e = hipMemset(d.diag, 0, 2 * sizeof(unsigned long long));
     if (e != hipSuccess) return hip_fail(e, "hipMemset(diag)");
+    e = hipMalloc((void**)&d.partial_pool, (size_t)kPartialSlots * kPartials * 5 * sizeof(double));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(partial pool)");
   }
   *out = &d;
   return 0;
@@ -95,10 +104,15 @@ int ensure_plain(Workspace& w, size_t bytes) {
   w.plain_bytes = bytes;
   return 0;
 }
-int ensure_partial(Workspace& w) {
+int ensure_partial(DeviceState& d, Workspace& w) {
   if (w.partial) return 0;
+  if (d.partial_used < kPartialSlots) {
+    w.partial = d.partial_pool + (size_t)(d.partial_used++) * kPartials * 5;
+    return 0;
+  }
   hipError_t e = hipMalloc((void**)&w.partial, (size_t)kPartials * 5 * sizeof(double));
   if (e != hipSuccess) return hip_fail(e, "hipMalloc(partials)");
+  w.own_partial = true;
   return 0;
 }
 template <typename T>
@@ -154,19 +168,26 @@ void tune_load() {
   fclose(f);
 }
 int cu_count() {
+  static std::map<int, int> cache;  // per device; read once (also safe under graph capture)
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
   int cus = 256;
   hipDeviceProp_t prop;
-  int dev;
-  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-    cus = prop.multiProcessorCount;
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+  cache[dev] = cus;
   return cus;
 }
 Tune tuned(int f64, int scheme, int recon, int riemann, int charlim, long long n_groups) {
   tune_load();
   auto it = g_tune.find(tune_key(f64, scheme, recon, riemann, charlim));
-  Tune t = (it != g_tune.end()) ? it->second : Tune{0, 2};
+  // Untuned default: the two-workgroups-per-CU register variant with six
+  // workgroups per CU in flight over the persistent loop (the autotuner's
+  // choice for CTU on MI355X); FP64 has one variant only.
+  Tune t = (it != g_tune.end()) ? it->second : Tune{0, 4};
   if (f64) t.waves = 2;
-  if (t.grid <= 0) t.grid = cu_count() * (t.waves == 4 ? 2 : 1);
+  if (t.grid <= 0) t.grid = cu_count() * (t.waves == 4 ? 6 : 1);
   if (t.grid > n_groups) t.grid = (int)n_groups;
   if (t.grid < 1) t.grid = 1;
   return t;
@@ -256,7 +277,7 @@ int hydro_solve_groups(const void* in, void* out, void* flux_out, int n_groups, 
     return 0;
   }
   // Fused path: a single segment passed by value, host dt included.
-  hy::Seg seg{in, out, flux_out, nullptr, 1.0, dh, 0, n_groups};
+  hy::Seg seg{in, out, flux_out, nullptr, 1.0, dh, 0, n_groups, 0, 0, 0, 0};
   const Tune tu = tuned(f64, scheme, reconstruction, riemann, (flags & HYDRO_CHAR) ? 1 : 0, n_groups);
   if (f64)
     return run_fused<double>(nullptr, 1, n_groups, g, scheme, reconstruction, riemann, limiter, flags, gamma,
@@ -294,6 +315,45 @@ int hydro_solve_batch(const struct hydro_seg* segs, int n_segs, long long n_grou
                           spec->limiter, spec->flags, spec->gamma, ds->diag, tu.grid, tu.waves, st);
 }
 
+int hydro_step_box(const void* box_in, void* box_out, void* flux_out, int nx, int ny, int nz, const double* dt_dev,
+                   double dt_scale, double dh, double gamma, int scheme, int reconstruction, int riemann, int limiter,
+                   int flags, void* stream) {
+  g_err[0] = 0;
+  if (int rc = check_options(scheme, reconstruction, riemann, limiter, flags)) return rc;
+  if (flags & HYDRO_PLAIN) return fail(HYDRO_EINVAL, "HYDRO_PLAIN is not a box path");
+  if (!box_in || !box_out || !dt_dev) return fail(HYDRO_EINVAL, "null pointer");
+  if (nx <= 0 || ny <= 0 || nz <= 0 || nx % 16 || ny % 16 || nz % 16)
+    return fail(HYDRO_EINVAL, "box sizes must be positive multiples of 16");
+  if (!(dh > 0.0) || !isfinite(dh) || !(dt_scale > 0.0) || !isfinite(dt_scale))
+    return fail(HYDRO_EINVAL, "dh and dt_scale must be positive and finite");
+  if (!(gamma > 1.0) || !isfinite(gamma)) return fail(HYDRO_EINVAL, "gamma must exceed 1");
+  const int charlim = (flags & HYDRO_CHAR) ? 1 : 0;
+  if (!hy::fused_supported(scheme, reconstruction, riemann, charlim))
+    return fail(HYDRO_EUNSUPPORTED, "box path not built for this combination");
+  const bool f64 = (flags & HYDRO_F64) != 0;
+  const size_t esz = f64 ? 8 : 4;
+  const long long G = (long long)(nx / 16) * (ny / 16) * (nz / 16);
+  const int nf = (flags & HYDRO_FLUX_MID) ? 3 : 2;
+  const size_t bb = (size_t)G * 5 * 4096 * esz, fb = (size_t)G * 3 * nf * 5 * 256 * esz;
+  if (overlap(box_in, bb, box_out, bb)) return fail(HYDRO_EALIAS, "box_in and box_out overlap");
+  if (flux_out && (overlap(flux_out, fb, box_in, bb) || overlap(flux_out, fb, box_out, bb)))
+    return fail(HYDRO_EALIAS, "flux_out overlaps a box");
+  hipStream_t st = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lock(g_mu);
+  DeviceState* ds;
+  if (int rc = device_state(&ds)) return rc;
+  hy::Seg seg{box_in, box_out, flux_out, dt_dev, dt_scale, dh, 0, G, nx / 16, ny / 16, nz / 16, 1};
+  const int g = ghost_width(scheme, reconstruction);
+  const Tune tu = tuned(f64, scheme, reconstruction, riemann, charlim, G);
+  // Passed by value: the kernel reads dt through seg.dt (segs == nullptr and
+  // a device dt pointer in seg0).
+  if (f64)
+    return run_fused<double>(nullptr, 1, G, g, scheme, reconstruction, riemann, limiter, flags, gamma, ds->diag,
+                             tu.grid, tu.waves, st, &seg, -1.0);
+  return run_fused<float>(nullptr, 1, G, g, scheme, reconstruction, riemann, limiter, flags, gamma, ds->diag, tu.grid,
+                          tu.waves, st, &seg, -1.0);
+}
+
 int hydro_cfl_dt(const void* U, int n_groups, double dh, double gamma, double cfl, int flags, double* dt_out,
                  void* stream) {
   g_err[0] = 0;
@@ -306,7 +366,7 @@ int hydro_cfl_dt(const void* U, int n_groups, double dh, double gamma, double cf
   DeviceState* ds;
   if (int rc = device_state(&ds)) return rc;
   Workspace& w = ds->ws[st];
-  if (int rc = ensure_partial(w)) return rc;
+  if (int rc = ensure_partial(*ds, w)) return rc;
   hipError_t e = (flags & HYDRO_F64)
                      ? hy::launch_maxspeed((const double*)U, n_groups, 4096, gamma, w.partial, kPartials, st)
                      : hy::launch_maxspeed((const float*)U, n_groups, 4096, gamma, w.partial, kPartials, st);
@@ -327,7 +387,7 @@ int hydro_conserved_sums(const void* U, int n_groups, double dh, int flags, doub
   DeviceState* ds;
   if (int rc = device_state(&ds)) return rc;
   Workspace& w = ds->ws[st];
-  if (int rc = ensure_partial(w)) return rc;
+  if (int rc = ensure_partial(*ds, w)) return rc;
   hipError_t e = (flags & HYDRO_F64)
                      ? hy::launch_sums((const double*)U, n_groups, 4096, dh, w.partial, kPartials, sums_out, st)
                      : hy::launch_sums((const float*)U, n_groups, 4096, dh, w.partial, kPartials, sums_out, st);
@@ -436,7 +496,7 @@ int hydro_autotune(const struct hydro_spec* spec, int n_groups_hint, void* strea
     for (long long q = 0; q < n && e == hipSuccess; ++q)
       e = hipMemcpyAsync((char*)in + q * host.size(), host.data(), host.size(), hipMemcpyHostToDevice, st);
     double dt = 1e-4;
-    hy::Seg s{in, out, nullptr, dtd, 1.0, 1.0 / 256, 0, n};
+    hy::Seg s{in, out, nullptr, dtd, 1.0, 1.0 / 256, 0, n, 0, 0, 0, 0};
     if (e == hipSuccess) e = hipMemcpyAsync(dtd, &dt, sizeof(dt), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(sd, &s, sizeof(s), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -505,9 +565,10 @@ void hydro_shutdown(void) {
     hipSetDevice(kv.first);
     for (auto& w : kv.second.ws) {
       if (w.second.plain) hipFree(w.second.plain);
-      if (w.second.partial) hipFree(w.second.partial);
+      if (w.second.partial && w.second.own_partial) hipFree(w.second.partial);
     }
     if (kv.second.diag) hipFree(kv.second.diag);
+    if (kv.second.partial_pool) hipFree(kv.second.partial_pool);
     hipSetDevice(prev);
   }
   g_dev.clear();

@@ -239,12 +239,22 @@ __global__ void __launch_bounds__(256) sums_kernel(const T* __restrict__ U, long
   }
 }
 
-__global__ void __launch_bounds__(64) sums_finish_kernel(const double* __restrict__ partial, int n, double vol,
+// Fixed-order finish: thread q adds partials q, q+256, ... in index order,
+// then a fixed shuffle tree and a fixed cross-wave sum.
+__global__ void __launch_bounds__(256) sums_finish_kernel(const double* __restrict__ partial, int n, double vol,
                                                          double* __restrict__ out) {
-  if (threadIdx.x < 5) {
+  __shared__ double red[5][4];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
     double s = 0.0;
-    for (int b = 0; b < n; ++b) s += partial[(long long)b * 5 + threadIdx.x];
-    out[threadIdx.x] = s * vol;
+    for (int b = threadIdx.x; b < n; b += blockDim.x) s += partial[(long long)b * 5 + v];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[v][threadIdx.x >> 6] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < 5) {
+    const int v = threadIdx.x;
+    out[v] = ((red[v][0] + red[v][1]) + (red[v][2] + red[v][3])) * vol;
   }
 }
 
@@ -255,7 +265,7 @@ hipError_t launch_sums(const T* U, long long n_blocks, long long cells, double d
   sums_kernel<T><<<dim3(n_partial), dim3(256), 0, st>>>(U, n_blocks, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  sums_finish_kernel<<<dim3(1), dim3(64), 0, st>>>(partial, n_partial, dh * dh * dh, sums_out);
+  sums_finish_kernel<<<dim3(1), dim3(256), 0, st>>>(partial, n_partial, dh * dh * dh, sums_out);
   return hipGetLastError();
 }
 template hipError_t launch_sums<float>(const float*, long long, long long, double, double*, int, double*, hipStream_t);

@@ -199,7 +199,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
       dt = *S->dt * S->dt_scale;
     } else {
       S = &a.seg0;
-      dt = a.dt0;
+      dt = S->dt ? *S->dt * S->dt_scale : a.dt0;
     }
     const long long lg = grp - S->first;
     const T* __restrict__ U = reinterpret_cast<const T*>(S->in) + lg * 5 * NC;
@@ -208,12 +208,33 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
     ph.dtdh = (T)(dt / S->dh);
     ph.hdtdh = (T)(0.5 * dt / S->dh);
 
-    auto gidx = [&](int x, int y, int z) -> long { return ((long)(z + G) * N + (y + G)) * N + (x + G); };
+    // Box mode: the group's cells, ghosts included, are read from the
+    // periodic grouped box itself (the preparation step fused into the
+    // solver); otherwise from the padded group input.
+    const bool box = S->box != 0;
+    const T* __restrict__ B = reinterpret_cast<const T*>(S->in);
+    const int bnx = S->ngx * 16, bny = S->ngy * 16, bnz = S->ngz * 16;
+    const int bx0 = box ? (int)(lg % S->ngx) * 16 : 0;
+    const int by0 = box ? (int)((lg / S->ngx) % S->ngy) * 16 : 0;
+    const int bz0 = box ? (int)(lg / ((long long)S->ngx * S->ngy)) * 16 : 0;
     auto load_cons = [&](int x, int y, int z) -> V5<T> {
-      const long q = gidx(x, y, z);
+      const T* p;
+      long stride;
+      if (box) {
+        int cx = bx0 + x, cy = by0 + y, cz = bz0 + z;
+        cx += cx < 0 ? bnx : 0; cx -= cx >= bnx ? bnx : 0;
+        cy += cy < 0 ? bny : 0; cy -= cy >= bny ? bny : 0;
+        cz += cz < 0 ? bnz : 0; cz -= cz >= bnz ? bnz : 0;
+        const long gq = ((long)(cz >> 4) * S->ngy + (cy >> 4)) * S->ngx + (cx >> 4);
+        p = B + gq * 5 * 4096 + (((cz & 15) * 16 + (cy & 15)) * 16 + (cx & 15));
+        stride = 4096;
+      } else {
+        p = U + ((long)(z + G) * N + (y + G)) * N + (x + G);
+        stride = NC;
+      }
       V5<T> u;
 #pragma unroll
-      for (int n = 0; n < 5; ++n) u[n] = U[n * NC + q];
+      for (int n = 0; n < 5; ++n) u[n] = p[n * stride];
       return u;
     };
     auto zprim = [&](int z) -> V5<T> { return to_frame<2>(prim_of(load_cons(col.x, col.y, z), ph)); };

@@ -35,6 +35,8 @@ struct Seg {
   double dh;
   long long first;   // first global group index of this segment
   long long count;
+  int ngx, ngy, ngz;  // box mode: groups per dimension of a periodic box
+  int box;            // 1: `in` is the box [G][5][16][16][16]; ghosts are read from it
 };
 
 // Fused (optimized) solver.  groups are addressed through segments; a plain

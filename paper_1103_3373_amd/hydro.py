@@ -24,6 +24,7 @@ F64, CHAR, FLUX_MID, PLAIN, ROE_FB_HLLC, BOX_GROUPED = 0x01, 0x02, 0x04, 0x08, 0
 EXPORTS = (
     "hydro_ghost_width", "hydro_solve_groups", "hydro_cfl_dt", "hydro_conserved_sums",
     "hydro_fill_ghosts_periodic", "hydro_fill_groups_interp", "hydro_solve_batch", "hydro_autotune",
+    "hydro_step_box",
     "hydro_get_diag", "hydro_last_error", "hydro_shutdown",
 )
 
@@ -37,7 +38,8 @@ class HydroError(RuntimeError):
 class Seg(ctypes.Structure):
     _fields_ = [("in_", ctypes.c_void_p), ("out", ctypes.c_void_p), ("flux", ctypes.c_void_p),
                 ("dt", ctypes.c_void_p), ("dt_scale", ctypes.c_double), ("dh", ctypes.c_double),
-                ("first", ctypes.c_longlong), ("count", ctypes.c_longlong)]
+                ("first", ctypes.c_longlong), ("count", ctypes.c_longlong),
+                ("ngx", ctypes.c_int), ("ngy", ctypes.c_int), ("ngz", ctypes.c_int), ("box", ctypes.c_int)]
 
 
 class Spec(ctypes.Structure):
@@ -73,6 +75,8 @@ def lib() -> ctypes.CDLL:
     L.hydro_fill_ghosts_periodic.restype = i
     L.hydro_fill_groups_interp.argtypes = [P, i, P, i, i, d, i, P, P]
     L.hydro_fill_groups_interp.restype = i
+    L.hydro_step_box.argtypes = [P, P, P, i, i, i, P, d, d, d, i, i, i, i, i, P]
+    L.hydro_step_box.restype = i
     L.hydro_solve_batch.argtypes = [P, i, ll, ctypes.POINTER(Spec), P]
     L.hydro_solve_batch.restype = i
     L.hydro_autotune.argtypes = [ctypes.POINTER(Spec), i, P]
@@ -206,14 +210,34 @@ def make_spec(scheme, recon, riemann, limiter=VANLEER, *, gamma, char=False, f64
 
 
 def seg_table(segs, device) -> torch.Tensor:
-    """Pack hydro_seg records [(in, out, flux|None, dt_tensor, dt_scale, dh, first, count)]
-    into a device byte tensor."""
+    """Pack hydro_seg records into a device byte tensor.  Each record is
+    (in, out, flux|None, dt_tensor, dt_scale, dh, first, count) for ghosted
+    groups, or with a trailing (ngx, ngy, ngz) for a periodic grouped box."""
     arr = (Seg * len(segs))()
-    for q, (i, o, f, dtt, sc, dh, first, count) in enumerate(segs):
+    for q, rec in enumerate(segs):
+        i, o, f, dtt, sc, dh, first, count = rec[:8]
+        box = rec[8] if len(rec) > 8 else None
         arr[q] = Seg(i.data_ptr(), o.data_ptr(), 0 if f is None else f.data_ptr(), dtt.data_ptr(), float(sc),
-                     float(dh), int(first), int(count))
+                     float(dh), int(first), int(count), *(box if box else (0, 0, 0)), 1 if box else 0)
     host = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8)
     return host.to(device)
+
+
+def step_box(box_in, box_out, shape, dt_dev, *, dh, gamma, scheme, recon, riemann, limiter=VANLEER, char=False,
+             dt_scale=1.0, flux=None, flux_mid=False, roe_fb_hllc=False, stream=None):
+    """One step of a periodic box in patch-group order [G,5,16,16,16]
+    (shape = (nx, ny, nz)); dt is read from the device double dt_dev."""
+    nx, ny, nz = shape
+    G = (nx // 16) * (ny // 16) * (nz // 16)
+    _require(box_in, "box_in", (G, 5, 16, 16, 16))
+    _require(box_out, "box_out", (G, 5, 16, 16, 16), box_in.dtype)
+    _require(dt_dev, "dt_dev", dtype=torch.float64)
+    flags = _dtype_flag(box_in) | (CHAR if char else 0) | (FLUX_MID if flux_mid else 0) \
+        | (ROE_FB_HLLC if roe_fb_hllc else 0)
+    _check("hydro_step_box", lib().hydro_step_box(_ptr(box_in), _ptr(box_out), _ptr(flux), nx, ny, nz,
+                                                  _ptr(dt_dev), float(dt_scale), float(dh), float(gamma), scheme,
+                                                  recon, riemann, limiter, flags, _stream(stream)))
+    return box_out
 
 
 def solve_batch(seg_dev: torch.Tensor, n_segs: int, n_groups_total: int, spec: Spec, stream=None):
