@@ -52,6 +52,8 @@ bool overlap(const void* a, size_t na, const void* b, size_t nb) {
 struct Workspace {
   void* plain = nullptr;
   size_t plain_bytes = 0;
+  void* vl = nullptr;  // VL half-step scratch (fused path)
+  size_t vl_bytes = 0;
   double* partial = nullptr;  // reduction partials (a pool slot or own memory)
   bool own_partial = false;
 };
@@ -104,6 +106,22 @@ int ensure_plain(Workspace& w, size_t bytes) {
   w.plain_bytes = bytes;
   return 0;
 }
+// VL scratch: grown on demand (an allocation, so the first VL call at a
+// given batch size must not be inside a graph capture).
+int ensure_vl(Workspace& w, size_t bytes) {
+  if (w.vl_bytes >= bytes) return 0;
+  if (w.vl) {
+    hipDeviceSynchronize();
+    hipFree(w.vl);
+    w.vl = nullptr;
+    w.vl_bytes = 0;
+  }
+  hipError_t e = hipMalloc(&w.vl, bytes);
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc(VL scratch)");
+  w.vl_bytes = bytes;
+  return 0;
+}
+
 int ensure_partial(DeviceState& d, Workspace& w) {
   if (w.partial) return 0;
   if (d.partial_used < kPartialSlots) {
@@ -196,7 +214,7 @@ Tune tuned(int f64, int scheme, int recon, int riemann, int charlim, long long n
 template <typename T>
 int run_fused(const hy::Seg* segs_dev, int n_segs, long long n_groups, int g, int scheme, int recon, int riemann,
               int limiter, int flags, double gamma, unsigned long long* diag, int grid, int waves, hipStream_t st,
-              const hy::Seg* seg0 = nullptr, double dt0 = 0.0) {
+              void* wstar, const hy::Seg* seg0 = nullptr, double dt0 = 0.0) {
   hy::FusedArgs<T> a;
   a.segs = segs_dev;
   a.n_segs = n_segs;
@@ -213,6 +231,7 @@ int run_fused(const hy::Seg* segs_dev, int n_segs, long long n_groups, int g, in
   if (seg0) a.seg0 = *seg0;
   else memset(&a.seg0, 0, sizeof(a.seg0));
   a.dt0 = dt0;
+  a.wstar = reinterpret_cast<T*>(wstar);
   hy::FusedCfg cfg;
   cfg.grid = grid;
   cfg.waves = waves;
@@ -279,11 +298,12 @@ int hydro_solve_groups(const void* in, void* out, void* flux_out, int n_groups, 
   // Fused path: a single segment passed by value, host dt included.
   hy::Seg seg{in, out, flux_out, nullptr, 1.0, dh, 0, n_groups, 0, 0, 0, 0};
   const Tune tu = tuned(f64, scheme, reconstruction, riemann, (flags & HYDRO_CHAR) ? 1 : 0, n_groups);
+  if (int rc = ensure_vl(w, (size_t)n_groups * hy::fused_scratch_per_group(scheme, reconstruction) * esz)) return rc;
   if (f64)
     return run_fused<double>(nullptr, 1, n_groups, g, scheme, reconstruction, riemann, limiter, flags, gamma,
-                             ds->diag, tu.grid, tu.waves, st, &seg, dt);
+                             ds->diag, tu.grid, tu.waves, st, w.vl, &seg, dt);
   return run_fused<float>(nullptr, 1, n_groups, g, scheme, reconstruction, riemann, limiter, flags, gamma, ds->diag,
-                          tu.grid, tu.waves, st, &seg, dt);
+                          tu.grid, tu.waves, st, w.vl, &seg, dt);
 }
 
 int hydro_solve_batch(const struct hydro_seg* segs, int n_segs, long long n_groups_total,
@@ -300,19 +320,23 @@ int hydro_solve_batch(const struct hydro_seg* segs, int n_segs, long long n_grou
   if (!hy::fused_supported(spec->scheme, spec->reconstruction, spec->riemann, charlim))
     return fail(HYDRO_EUNSUPPORTED, "fused path not built for this combination");
   static_assert(sizeof(hydro_seg) == sizeof(hy::Seg), "segment layout");
+  hipStream_t st = (hipStream_t)stream;
   std::lock_guard<std::mutex> lock(g_mu);
   DeviceState* ds;
   if (int rc = device_state(&ds)) return rc;
   const bool f64 = (spec->flags & HYDRO_F64) != 0;
   const int g = ghost_width(spec->scheme, spec->reconstruction);
   const Tune tu = tuned(f64, spec->scheme, spec->reconstruction, spec->riemann, charlim, n_groups_total);
+  Workspace& w = ds->ws[st];
+  if (int rc = ensure_vl(w, (size_t)n_groups_total * hy::fused_scratch_per_group(spec->scheme, spec->reconstruction) *
+                                (f64 ? 8 : 4)))
+    return rc;
   const hy::Seg* sd = (const hy::Seg*)segs;
-  hipStream_t st = (hipStream_t)stream;
   if (f64)
     return run_fused<double>(sd, n_segs, n_groups_total, g, spec->scheme, spec->reconstruction, spec->riemann,
-                             spec->limiter, spec->flags, spec->gamma, ds->diag, tu.grid, tu.waves, st);
+                             spec->limiter, spec->flags, spec->gamma, ds->diag, tu.grid, tu.waves, st, w.vl);
   return run_fused<float>(sd, n_segs, n_groups_total, g, spec->scheme, spec->reconstruction, spec->riemann,
-                          spec->limiter, spec->flags, spec->gamma, ds->diag, tu.grid, tu.waves, st);
+                          spec->limiter, spec->flags, spec->gamma, ds->diag, tu.grid, tu.waves, st, w.vl);
 }
 
 int hydro_step_box(const void* box_in, void* box_out, void* flux_out, int nx, int ny, int nz, const double* dt_dev,
@@ -345,13 +369,15 @@ int hydro_step_box(const void* box_in, void* box_out, void* flux_out, int nx, in
   hy::Seg seg{box_in, box_out, flux_out, dt_dev, dt_scale, dh, 0, G, nx / 16, ny / 16, nz / 16, 1};
   const int g = ghost_width(scheme, reconstruction);
   const Tune tu = tuned(f64, scheme, reconstruction, riemann, charlim, G);
+  Workspace& w = ds->ws[st];
+  if (int rc = ensure_vl(w, (size_t)G * hy::fused_scratch_per_group(scheme, reconstruction) * esz)) return rc;
   // Passed by value: the kernel reads dt through seg.dt (segs == nullptr and
   // a device dt pointer in seg0).
   if (f64)
     return run_fused<double>(nullptr, 1, G, g, scheme, reconstruction, riemann, limiter, flags, gamma, ds->diag,
-                             tu.grid, tu.waves, st, &seg, -1.0);
+                             tu.grid, tu.waves, st, w.vl, &seg, -1.0);
   return run_fused<float>(nullptr, 1, G, g, scheme, reconstruction, riemann, limiter, flags, gamma, ds->diag, tu.grid,
-                          tu.waves, st, &seg, -1.0);
+                          tu.waves, st, w.vl, &seg, -1.0);
 }
 
 int hydro_cfl_dt(const void* U, int n_groups, double dh, double gamma, double cfl, int flags, double* dt_out,
@@ -503,9 +529,16 @@ int hydro_autotune(const struct hydro_spec* spec, int n_groups_hint, void* strea
   }
   const int cus = cu_count();
   DeviceState* ds = nullptr;
+  void* vl = nullptr;
   {
     std::lock_guard<std::mutex> lock(g_mu);
     if (int rc = device_state(&ds)) { hipFree(in); hipFree(out); hipFree(dtd); hipFree(sd); return rc; }
+    Workspace& w = ds->ws[st];
+    if (int rc = ensure_vl(w, (size_t)n * hy::fused_scratch_per_group(spec->scheme, spec->reconstruction) * esz)) {
+      hipFree(in); hipFree(out); hipFree(dtd); hipFree(sd);
+      return rc;
+    }
+    vl = w.vl;
   }
   // Candidates: register variant x persistent grid (multiples of the CU count).
   const int mults[] = {1, 2, 3, 4, 6, 8};
@@ -525,9 +558,9 @@ int hydro_autotune(const struct hydro_spec* spec, int n_groups_hint, void* strea
       for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
         e = hipEventRecord(e0, st);
         int rc = f64 ? run_fused<double>(sd, 1, n, g, spec->scheme, spec->reconstruction, spec->riemann,
-                                         spec->limiter, spec->flags, spec->gamma, ds->diag, (int)grid, wv, st)
+                                         spec->limiter, spec->flags, spec->gamma, ds->diag, (int)grid, wv, st, vl)
                      : run_fused<float>(sd, 1, n, g, spec->scheme, spec->reconstruction, spec->riemann,
-                                        spec->limiter, spec->flags, spec->gamma, ds->diag, (int)grid, wv, st);
+                                        spec->limiter, spec->flags, spec->gamma, ds->diag, (int)grid, wv, st, vl);
         if (rc) { e = hipErrorLaunchFailure; break; }
         if (e == hipSuccess) e = hipEventRecord(e1, st);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -565,6 +598,7 @@ void hydro_shutdown(void) {
     hipSetDevice(kv.first);
     for (auto& w : kv.second.ws) {
       if (w.second.plain) hipFree(w.second.plain);
+      if (w.second.vl) hipFree(w.second.vl);
       if (w.second.partial && w.second.own_partial) hipFree(w.second.partial);
     }
     if (kv.second.diag) hipFree(kv.second.diag);

@@ -1,0 +1,189 @@
+// Pieces shared by the fused z-marching kernels (CTU, MHM, VL): LDS
+// helpers, the thread -> column map of a 512-thread workgroup over the 16x16
+// interior plus rings, segment lookup, and loads of a group's cells either
+// from a ghosted group array or, in box mode, from the periodic grouped box.
+#pragma once
+
+#include "hydro_internal.h"
+#include "hydro_math.hpp"
+
+namespace hy {
+namespace fz {
+
+constexpr int kThreads = 512;
+
+template <typename T> HY_DEV V5<T> lds5(const T* s, int stride, int i) {
+  V5<T> v;
+#pragma unroll
+  for (int n = 0; n < 5; ++n) v[n] = s[n * stride + i];
+  return v;
+}
+template <typename T> HY_DEV void sts5(T* s, int stride, int i, const V5<T>& v) {
+#pragma unroll
+  for (int n = 0; n < 5; ++n) s[n * stride + i] = v[n];
+}
+template <typename T> HY_DEV V5<T> sub5(const V5<T>& a, const V5<T>& b) {
+  V5<T> r;
+#pragma unroll
+  for (int n = 0; n < 5; ++n) r[n] = a[n] - b[n];
+  return r;
+}
+
+// Face values of one cell from its neighbourhood along a direction (frame
+// states), PLM or PPM, before tracing.  wm/wp are the neighbours, sm/s0/sp
+// the limited slopes of the neighbours and the cell (PLM uses s0 only).
+template <bool PPM, typename T>
+HY_DEV void face_values(const V5<T>& wm, const V5<T>& w0, const V5<T>& wp, const V5<T>& sm, const V5<T>& s0,
+                        const V5<T>& sp, const Phys<T>& ph, V5<T>& fl, V5<T>& fr) {
+  if (PPM) {
+    fl = ppm_edge(wm, w0, sm, s0);
+    fr = ppm_edge(w0, wp, s0, sp);
+    ppm_mono(w0, fl, fr);
+  } else {
+    plm_faces(wm, w0, wp, s0, ph, fl, fr);
+  }
+}
+
+// Corrected state: U(W) - hdtdh * d, back to primitive with floors.
+template <typename T>
+HY_DEV V5<T> correct(const V5<T>& W, const V5<T>& d, const Phys<T>& ph, int& floors) {
+  V5<T> u = cons_of(W, ph);
+#pragma unroll
+  for (int n = 0; n < 5; ++n) u[n] -= ph.hdtdh * d[n];
+  V5<T> w = prim_of(u, ph);
+  floors += floor_state(w, ph);
+  return w;
+}
+
+template <typename T> struct Column {
+  int x, y;      // interior-relative coordinates
+  int cross;     // 1 if the column needs z work (interior + 1-cell ring)
+  int active;    // 1 if the column feeds the primitive plane
+};
+
+template <int G> HY_DEV Column<int> column_of(int tid) {
+  Column<int> c{0, 0, 0, 0};
+  if (tid < 256) {
+    c.x = tid & 15; c.y = tid >> 4; c.cross = 1; c.active = 1;
+  } else if (tid < 320) {
+    int q = tid - 256, s = q & 15;
+    switch (q >> 4) {
+      case 0: c.x = -1; c.y = s; break;
+      case 1: c.x = 16; c.y = s; break;
+      case 2: c.x = s; c.y = -1; break;
+      default: c.x = s; c.y = 16; break;
+    }
+    c.cross = 1; c.active = 1;
+  } else if (tid < 324) {
+    int q = tid - 320;
+    c.x = (q & 1) ? 16 : -1; c.y = (q & 2) ? 16 : -1; c.active = 1;
+  } else {
+    // Outer columns: G-1 per side beyond the ring, 18 long, along both axes.
+    const int w = G - 1;               // 2 for PPM, 1 for PLM
+    const int per = 2 * w * 18;        // one orientation
+    int q = tid - 324;
+    if (q < 2 * per) {
+      int o = q / per, r = q % per;
+      int side = r / (w * 18), rr = r % (w * 18);
+      int depth = rr / 18, along = rr % 18 - 1;   // along in -1..16
+      int off = side ? (17 + depth) : (-2 - depth);
+      if (o == 0) { c.x = off; c.y = along; }
+      else { c.x = along; c.y = off; }
+      c.active = 1;
+    }
+  }
+  return c;
+}
+
+
+// Per-launch physics constants (dt/dh set per group from its segment).
+template <typename T> HY_DEV Phys<T> make_phys(const FusedArgs<T>& a) {
+  Phys<T> ph;
+  ph.gamma = a.gamma;
+  ph.gm1 = a.gamma - T(1);
+  ph.inv_gm1 = T(1) / ph.gm1;
+  ph.theta = a.theta;
+  ph.floor = a.floor;
+  ph.limiter = a.limiter;
+  ph.charlim = a.charlim;
+  ph.roe_fb_hllc = a.roe_fb_hllc;
+  ph.dtdh = T(0);
+  ph.hdtdh = T(0);
+  return ph;
+}
+
+// Segment of global group grp (segments sorted by first group; `seg` is a
+// cursor that only moves forward in a persistent loop) and its time step.
+template <typename T>
+HY_DEV const Seg* find_seg(const FusedArgs<T>& a, long long grp, int& seg, double& dt) {
+  const Seg* S;
+  if (a.segs) {
+    while (seg + 1 < a.n_segs && a.segs[seg + 1].first <= grp) ++seg;
+    while (seg > 0 && a.segs[seg].first > grp) --seg;
+    S = &a.segs[seg];
+    dt = *S->dt * S->dt_scale;
+  } else {
+    S = &a.seg0;
+    dt = S->dt ? *S->dt * S->dt_scale : a.dt0;
+  }
+  return S;
+}
+
+// Reader of the conserved cells of one column (x, y fixed, interior-relative)
+// of one group: a ghosted group array of width G (N = 16 + 2G), or, in box
+// mode, the periodic box stored as groups.  The (x, y) part of the address
+// is formed once per group; a load only adds the z part.
+template <typename T, int G> struct ColumnReader {
+  static constexpr int N = 16 + 2 * G;
+  static constexpr long NC = (long)N * N * N;
+  const T* col;     // address of the column's cell at z = 0 (box: of the z-group 0 slab)
+  bool box;
+  int bz0, bnz;     // box mode: first z of the group, box size in z
+  long zgs;         // box mode: elements between z-neighbouring groups
+  HY_DEV void init(const Seg* S, long long lg, int x, int y) {
+    box = S->box != 0;
+    if (box) {
+      const int ngx = S->ngx, ngy = S->ngy;
+      const int bnx = ngx * 16, bny = ngy * 16;
+      bnz = S->ngz * 16;
+      const int bx0 = (int)(lg % ngx) * 16, by0 = (int)((lg / ngx) % ngy) * 16;
+      bz0 = (int)(lg / ((long long)ngx * ngy)) * 16;
+      int cx = bx0 + x, cy = by0 + y;
+      cx += cx < 0 ? bnx : 0; cx -= cx >= bnx ? bnx : 0;
+      cy += cy < 0 ? bny : 0; cy -= cy >= bny ? bny : 0;
+      zgs = (long)ngx * ngy * 5 * 4096;
+      col = reinterpret_cast<const T*>(S->in) + ((long)(cy >> 4) * ngx + (cx >> 4)) * 5 * 4096 +
+            ((cy & 15) * 16 + (cx & 15));
+    } else {
+      col = reinterpret_cast<const T*>(S->in) + lg * 5 * NC + (long)(y + G) * N + (x + G) + (long)G * N * N;
+      bz0 = bnz = 0;
+      zgs = 0;
+    }
+  }
+  HY_DEV V5<T> load(int z) const {
+    V5<T> u;
+    if (box) {
+      int cz = bz0 + z;
+      cz += cz < 0 ? bnz : 0;
+      cz -= cz >= bnz ? bnz : 0;
+      const T* p = col + (cz >> 4) * zgs + (cz & 15) * 256;
+#pragma unroll
+      for (int n = 0; n < 5; ++n) u[n] = p[n * 4096];
+    } else {
+      const T* p = col + (long)z * N * N;
+#pragma unroll
+      for (int n = 0; n < 5; ++n) u[n] = p[n * NC];
+    }
+    return u;
+  }
+};
+
+template <typename T> HY_DEV void flush_diag(const FusedArgs<T>& a, int fails, int floors) {
+  if (a.diag) {
+    if (fails) atomicAdd(&a.diag[0], (unsigned long long)fails);
+    if (floors) atomicAdd(&a.diag[1], (unsigned long long)floors);
+  }
+}
+
+}  // namespace fz
+}  // namespace hy

@@ -28,13 +28,12 @@
 // the optional face fluxes.
 #pragma once
 
-#include "hydro_internal.h"
-#include "hydro_math.hpp"
+#include "fused_common.hpp"
 
 namespace hy {
 namespace ctu {
 
-constexpr int kThreads = 512;
+using namespace fz;
 
 // LDS layout (elements of T).  Sizes are those of PPM (g = 3); PLM uses a
 // subset of the same layout.
@@ -61,89 +60,6 @@ constexpr int oF2 = oSX;
 constexpr int oG2 = oSX + 5 * kF2;
 static_assert(10 * kF2 <= 5 * (kSX + kSY), "F2/G2 alias");
 
-template <typename T> HY_DEV V5<T> lds5(const T* s, int stride, int i) {
-  V5<T> v;
-#pragma unroll
-  for (int n = 0; n < 5; ++n) v[n] = s[n * stride + i];
-  return v;
-}
-template <typename T> HY_DEV void sts5(T* s, int stride, int i, const V5<T>& v) {
-#pragma unroll
-  for (int n = 0; n < 5; ++n) s[n * stride + i] = v[n];
-}
-template <typename T> HY_DEV V5<T> sub5(const V5<T>& a, const V5<T>& b) {
-  V5<T> r;
-#pragma unroll
-  for (int n = 0; n < 5; ++n) r[n] = a[n] - b[n];
-  return r;
-}
-
-// Face values of one cell from its neighbourhood along a direction (frame
-// states), PLM or PPM, before tracing.  wm/wp are the neighbours, sm/s0/sp
-// the limited slopes of the neighbours and the cell (PLM uses s0 only).
-template <bool PPM, typename T>
-HY_DEV void face_values(const V5<T>& wm, const V5<T>& w0, const V5<T>& wp, const V5<T>& sm, const V5<T>& s0,
-                        const V5<T>& sp, const Phys<T>& ph, V5<T>& fl, V5<T>& fr) {
-  if (PPM) {
-    fl = ppm_edge(wm, w0, sm, s0);
-    fr = ppm_edge(w0, wp, s0, sp);
-    ppm_mono(w0, fl, fr);
-  } else {
-    plm_faces(wm, w0, wp, s0, ph, fl, fr);
-  }
-}
-
-// Corrected state: U(W) - hdtdh * d, back to primitive with floors.
-template <typename T>
-HY_DEV V5<T> correct(const V5<T>& W, const V5<T>& d, const Phys<T>& ph, int& floors) {
-  V5<T> u = cons_of(W, ph);
-#pragma unroll
-  for (int n = 0; n < 5; ++n) u[n] -= ph.hdtdh * d[n];
-  V5<T> w = prim_of(u, ph);
-  floors += floor_state(w, ph);
-  return w;
-}
-
-template <typename T> struct Column {
-  int x, y;      // interior-relative coordinates
-  int cross;     // 1 if the column needs z work (interior + 1-cell ring)
-  int active;    // 1 if the column feeds the primitive plane
-};
-
-template <int G> HY_DEV Column<int> column_of(int tid) {
-  Column<int> c{0, 0, 0, 0};
-  if (tid < 256) {
-    c.x = tid & 15; c.y = tid >> 4; c.cross = 1; c.active = 1;
-  } else if (tid < 320) {
-    int q = tid - 256, s = q & 15;
-    switch (q >> 4) {
-      case 0: c.x = -1; c.y = s; break;
-      case 1: c.x = 16; c.y = s; break;
-      case 2: c.x = s; c.y = -1; break;
-      default: c.x = s; c.y = 16; break;
-    }
-    c.cross = 1; c.active = 1;
-  } else if (tid < 324) {
-    int q = tid - 320;
-    c.x = (q & 1) ? 16 : -1; c.y = (q & 2) ? 16 : -1; c.active = 1;
-  } else {
-    // Outer columns: G-1 per side beyond the ring, 18 long, along both axes.
-    const int w = G - 1;               // 2 for PPM, 1 for PLM
-    const int per = 2 * w * 18;        // one orientation
-    int q = tid - 324;
-    if (q < 2 * per) {
-      int o = q / per, r = q % per;
-      int side = r / (w * 18), rr = r % (w * 18);
-      int depth = rr / 18, along = rr % 18 - 1;   // along in -1..16
-      int off = side ? (17 + depth) : (-2 - depth);
-      if (o == 0) { c.x = off; c.y = along; }
-      else { c.x = along; c.y = off; }
-      c.active = 1;
-    }
-  }
-  return c;
-}
-
 // WAVES = minimum waves per SIMD the register allocation must allow: 2 gives
 // one workgroup per CU without spills, 4 gives two workgroups per CU (with
 // some spilling); the autotuner picks per specialization.
@@ -151,7 +67,6 @@ template <typename T, bool PPM, int RS, int WAVES>
 __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T> a) {
   constexpr int G = PPM ? 3 : 2;
   constexpr int N = 16 + 2 * G;
-  constexpr long NC = (long)N * N * N;
   extern __shared__ unsigned char smem_raw[];
   T* sm = reinterpret_cast<T*>(smem_raw);
   T* sP = sm + oP;
@@ -172,15 +87,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
   const bool interior = tid < 256;
   int fails = 0, floors = 0;
 
-  Phys<T> ph;
-  ph.gamma = a.gamma;
-  ph.gm1 = a.gamma - T(1);
-  ph.inv_gm1 = T(1) / ph.gm1;
-  ph.theta = a.theta;
-  ph.floor = a.floor;
-  ph.limiter = a.limiter;
-  ph.charlim = a.charlim;
-  ph.roe_fb_hllc = a.roe_fb_hllc;
+  Phys<T> ph = make_phys(a);
 
   // Slope task counts (PLM needs slopes of the traced cells only).
   constexpr int wSX = PPM ? 20 : 18, x0SX = PPM ? -2 : -1;
@@ -190,53 +97,18 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
 
   int seg = 0;
   for (long long grp = blockIdx.x; grp < a.n_groups; grp += gridDim.x) {
-    const Seg* S;
     double dt;
-    if (a.segs) {  // segments are sorted by their first group
-      while (seg + 1 < a.n_segs && a.segs[seg + 1].first <= grp) ++seg;
-      while (seg > 0 && a.segs[seg].first > grp) --seg;
-      S = &a.segs[seg];
-      dt = *S->dt * S->dt_scale;
-    } else {
-      S = &a.seg0;
-      dt = S->dt ? *S->dt * S->dt_scale : a.dt0;
-    }
+    const Seg* S = find_seg(a, grp, seg, dt);
     const long long lg = grp - S->first;
-    const T* __restrict__ U = reinterpret_cast<const T*>(S->in) + lg * 5 * NC;
     T* __restrict__ O = reinterpret_cast<T*>(S->out) + lg * 5 * 4096;
     T* __restrict__ FO = S->flux ? reinterpret_cast<T*>(S->flux) + lg * 3 * a.nf * 5 * 256 : nullptr;
     ph.dtdh = (T)(dt / S->dh);
     ph.hdtdh = (T)(0.5 * dt / S->dh);
-
-    // Box mode: the group's cells, ghosts included, are read from the
-    // periodic grouped box itself (the preparation step fused into the
-    // solver); otherwise from the padded group input.
-    const bool box = S->box != 0;
-    const T* __restrict__ B = reinterpret_cast<const T*>(S->in);
-    const int bnx = S->ngx * 16, bny = S->ngy * 16, bnz = S->ngz * 16;
-    const int bx0 = box ? (int)(lg % S->ngx) * 16 : 0;
-    const int by0 = box ? (int)((lg / S->ngx) % S->ngy) * 16 : 0;
-    const int bz0 = box ? (int)(lg / ((long long)S->ngx * S->ngy)) * 16 : 0;
-    auto load_cons = [&](int x, int y, int z) -> V5<T> {
-      const T* p;
-      long stride;
-      if (box) {
-        int cx = bx0 + x, cy = by0 + y, cz = bz0 + z;
-        cx += cx < 0 ? bnx : 0; cx -= cx >= bnx ? bnx : 0;
-        cy += cy < 0 ? bny : 0; cy -= cy >= bny ? bny : 0;
-        cz += cz < 0 ? bnz : 0; cz -= cz >= bnz ? bnz : 0;
-        const long gq = ((long)(cz >> 4) * S->ngy + (cy >> 4)) * S->ngx + (cx >> 4);
-        p = B + gq * 5 * 4096 + (((cz & 15) * 16 + (cy & 15)) * 16 + (cx & 15));
-        stride = 4096;
-      } else {
-        p = U + ((long)(z + G) * N + (y + G)) * N + (x + G);
-        stride = NC;
-      }
-      V5<T> u;
-#pragma unroll
-      for (int n = 0; n < 5; ++n) u[n] = p[n * stride];
-      return u;
-    };
+    // The group's cells (ghosts included) come from the ghosted input or, in
+    // box mode, straight from the periodic grouped box.
+    ColumnReader<T, G> rd;
+    rd.init(S, lg, col.x, col.y);
+    auto load_cons = [&](int x, int y, int z) -> V5<T> { return rd.load(z); };
     auto zprim = [&](int z) -> V5<T> { return to_frame<2>(prim_of(load_cons(col.x, col.y, z), ph)); };
 
     // Register state of a cross column (frame z unless noted):
@@ -461,10 +333,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
     }
     __syncthreads();
   }
-  if (a.diag) {
-    if (fails) atomicAdd(&a.diag[0], (unsigned long long)fails);
-    if (floors) atomicAdd(&a.diag[1], (unsigned long long)floors);
-  }
+  flush_diag(a, fails, floors);
 }
 
 }  // namespace ctu

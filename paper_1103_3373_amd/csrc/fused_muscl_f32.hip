@@ -1,0 +1,66 @@
+// Instantiations of the fused MHM / VL-second-stage kernel and the VL
+// predictor for float.
+#include "fused_muscl.hpp"
+#include "fused_vlpred.hpp"
+
+namespace hy {
+
+template <int MODE, bool PPM, int RS, int WAVES>
+static hipError_t launch_one(const FusedArgs<float>& a, int grid, hipStream_t st) {
+  auto k = muscl::muscl_kernel<float, PPM, RS, WAVES, MODE>;
+  const size_t shm = (size_t)muscl::kLds * sizeof(float);
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  k<<<dim3(grid), dim3(fz::kThreads), shm, st>>>(a);
+  return hipGetLastError();
+}
+
+template <int MODE, int WAVES>
+static hipError_t launch_w(const FusedArgs<float>& a, int recon, int riemann, int grid, hipStream_t st) {
+  if (recon == 1) {
+    if (riemann == 0) return launch_one<MODE, true, 0, WAVES>(a, grid, st);
+    if (riemann == 1) return launch_one<MODE, true, 1, WAVES>(a, grid, st);
+    return launch_one<MODE, true, 2, WAVES>(a, grid, st);
+  }
+  if (riemann == 0) return launch_one<MODE, false, 0, WAVES>(a, grid, st);
+  if (riemann == 1) return launch_one<MODE, false, 1, WAVES>(a, grid, st);
+  return launch_one<MODE, false, 2, WAVES>(a, grid, st);
+}
+
+hipError_t launch_muscl_f32(const FusedArgs<float>& a, int mode, int recon, int riemann, const FusedCfg& cfg,
+                             hipStream_t st) {
+  if (cfg.waves == 4)
+    return mode == 0 ? launch_w<0, 4>(a, recon, riemann, cfg.grid, st) : launch_w<1, 4>(a, recon, riemann, cfg.grid, st);
+  return mode == 0 ? launch_w<0, 2>(a, recon, riemann, cfg.grid, st) : launch_w<1, 2>(a, recon, riemann, cfg.grid, st);
+}
+
+template <bool PPM, int RS>
+static hipError_t launch_pred(const FusedArgs<float>& a, int grid, hipStream_t st) {
+  auto k = vlpred::vl_predict_kernel<float, PPM, RS>;
+  const size_t shm = (size_t)vlpred::lds_elems<PPM>() * sizeof(float);
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  k<<<dim3(grid), dim3(vlpred::kThreads), shm, st>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_vlpred_f32(const FusedArgs<float>& a, int recon, int riemann, int grid, hipStream_t st) {
+  if (recon == 1) {
+    if (riemann == 0) return launch_pred<true, 0>(a, grid, st);
+    if (riemann == 1) return launch_pred<true, 1>(a, grid, st);
+    return launch_pred<true, 2>(a, grid, st);
+  }
+  if (riemann == 0) return launch_pred<false, 0>(a, grid, st);
+  if (riemann == 1) return launch_pred<false, 1>(a, grid, st);
+  return launch_pred<false, 2>(a, grid, st);
+}
+
+}  // namespace hy

@@ -1,0 +1,125 @@
+// First stage of the VL scheme (arXiv:1103.3373, Sec. 2): Riemann fluxes on
+// piecewise-constant data at every face, then the unsplit half step
+//   W* = W(U^n - dt/(2dh) sum_d (F1_{d,+} - F1_{d,-}))   (with floors)
+// on every cell that the second stage reconstructs from, i.e. the group
+// interior plus g-1 ghost layers.  W* goes to a scratch array laid out as
+// ghosted groups [group][5][N'][N'][N'], N' = 16 + 2(g-1).
+//
+// One workgroup per group marching along z; a thread per (x, y) column of
+// the padded input plane keeps U and W of planes z, z+1 and the z face flux
+// below in registers; x and y face fluxes of the plane go through LDS, each
+// computed once.  Two barriers per plane.
+#pragma once
+
+#include "fused_common.hpp"
+
+namespace hy {
+namespace vlpred {
+
+using namespace fz;
+
+constexpr int kThreads = 576;  // one thread per column of the 24 x 24 padded plane (PPM)
+
+template <typename T, bool PPM, int RS>
+__global__ void __launch_bounds__(kThreads, 2) vl_predict_kernel(FusedArgs<T> a) {
+  constexpr int G = PPM ? 4 : 3;   // input ghost width
+  constexpr int N = 16 + 2 * G;
+  constexpr int Gs = G - 1;        // output ghost width
+  constexpr int Ns = 16 + 2 * Gs;
+  constexpr long NCs = (long)Ns * Ns * Ns;
+  constexpr int nF = (N - 1) * Ns;  // x faces between x = i and i+1, i in -G .. 14+G; rows -Gs .. 15+Gs
+  extern __shared__ unsigned char smem_raw[];
+  T* sm = reinterpret_cast<T*>(smem_raw);
+  T* sP = sm;                       // [5][N*N]
+  T* sFX = sP + 5 * N * N;          // [5][nF]   index (y + Gs) * (N - 1) + (i + G)
+  T* sFY = sFX + 5 * nF;            // [5][nF]   index (j + G) * Ns + (x + Gs)
+
+  const int tid = threadIdx.x;
+  const bool active = tid < N * N;
+  const int x = tid % N - G, y = tid / N - G;
+  const bool out_col = active && x >= -Gs && x <= 15 + Gs && y >= -Gs && y <= 15 + Gs;
+  int fails = 0, floors = 0;
+  Phys<T> ph = make_phys(a);
+
+  int seg = 0;
+  for (long long grp = blockIdx.x; grp < a.n_groups; grp += gridDim.x) {
+    double dt;
+    const Seg* S = find_seg(a, grp, seg, dt);
+    const long long lg = grp - S->first;
+    ph.dtdh = (T)(dt / S->dh);
+    ph.hdtdh = (T)(0.5 * dt / S->dh);
+    ColumnReader<T, G> rd;
+    rd.init(S, lg, active ? x : 0, active ? y : 0);
+    T* __restrict__ Wo = a.wstar + grp * 5 * NCs + ((long)(y + Gs) * Ns + (x + Gs));
+
+    V5<T> u0, w0, u1, w1, hm;
+    if (active) {
+      u0 = rd.load(-Gs - 1);
+      w0 = prim_of(u0, ph);
+      u1 = rd.load(-Gs);
+      w1 = prim_of(u1, ph);
+      if (out_col) hm = from_frame<2>(riemann<RS>(to_frame<2>(w0), to_frame<2>(w1), ph, &fails));
+      u0 = u1;
+      w0 = w1;
+    }
+    for (int z = -Gs; z <= 15 + Gs; ++z) {
+      // ---- A: plane z to LDS; z flux above the column's cell ----------------
+      V5<T> hp;
+      if (active) {
+        sts5(sP, N * N, tid, w0);
+        u1 = rd.load(z + 1);
+        w1 = prim_of(u1, ph);
+        if (out_col) hp = from_frame<2>(riemann<RS>(to_frame<2>(w0), to_frame<2>(w1), ph, &fails));
+      }
+      __syncthreads();
+      // ---- B: x and y face fluxes of plane z --------------------------------
+      for (int q = tid; q < 2 * nF; q += kThreads) {
+        if (q < nF) {
+          const int i = q % (N - 1) - G, r = q / (N - 1) - Gs;  // face between i and i+1, row r
+          const int c = (r + G) * N + (i + G);
+          V5<T> F = riemann<RS>(to_frame<0>(lds5(sP, N * N, c)), to_frame<0>(lds5(sP, N * N, c + 1)), ph, &fails);
+          sts5(sFX, nF, q, from_frame<0>(F));
+        } else {
+          const int qq = q - nF;
+          const int cx = qq % Ns - Gs, j = qq / Ns - G;  // face between j and j+1, column cx
+          const int c = (j + G) * N + (cx + G);
+          V5<T> F = riemann<RS>(to_frame<1>(lds5(sP, N * N, c)), to_frame<1>(lds5(sP, N * N, c + N)), ph, &fails);
+          sts5(sFY, nF, qq, from_frame<1>(F));
+        }
+      }
+      __syncthreads();
+      // ---- C: half-step state of the column's cell --------------------------
+      if (out_col) {
+        const int fx = (y + Gs) * (N - 1) + (x + G);   // face x+1/2; x-1/2 is fx - 1
+        const int fy = (y + G) * Ns + (x + Gs);        // face y+1/2; y-1/2 is fy - Ns
+        V5<T> dx = sub5(lds5(sFX, nF, fx), lds5(sFX, nF, fx - 1));
+        V5<T> dy = sub5(lds5(sFY, nF, fy), lds5(sFY, nF, fy - Ns));
+        V5<T> u = u0;
+#pragma unroll
+        for (int n = 0; n < 5; ++n) u[n] -= ph.hdtdh * (dx[n] + dy[n] + (hp[n] - hm[n]));
+        V5<T> w = prim_of(u, ph);
+        floors += floor_state(w, ph);
+        T* o = Wo + (long)(z + Gs) * Ns * Ns;
+#pragma unroll
+        for (int n = 0; n < 5; ++n) o[n * NCs] = w[n];
+        hm = hp;
+      }
+      if (active) {
+        u0 = u1;
+        w0 = w1;
+      }
+    }
+    __syncthreads();
+  }
+  flush_diag(a, fails, floors);
+}
+
+template <bool PPM> constexpr int lds_elems() {
+  constexpr int G = PPM ? 4 : 3;
+  constexpr int N = 16 + 2 * G;
+  constexpr int Ns = 16 + 2 * (G - 1);
+  return 5 * N * N + 10 * (N - 1) * Ns;
+}
+
+}  // namespace vlpred
+}  // namespace hy

@@ -54,6 +54,8 @@ struct FusedArgs {
   // (segs == nullptr), so no table upload is needed.
   Seg seg0;
   double dt0;
+  // VL: scratch for the half-step primitive state, [n_groups][5][N'^3].
+  T* wstar;
 };
 
 struct FusedCfg {
@@ -62,6 +64,8 @@ struct FusedCfg {
 };
 
 bool fused_supported(int scheme, int recon, int riemann, int charlim);
+// Elements of T per group of the VL half-step scratch (0 for other schemes).
+long long fused_scratch_per_group(int scheme, int recon);
 hipError_t launch_fused(const FusedArgs<float>& a, int scheme, int recon, int riemann, const FusedCfg& cfg,
                         hipStream_t st);
 hipError_t launch_fused(const FusedArgs<double>& a, int scheme, int recon, int riemann, const FusedCfg& cfg,

@@ -32,32 +32,33 @@ def _dev(a, dtype):
     return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
 
 
+@pytest.mark.parametrize("scheme", [0, 1, 2])
 @pytest.mark.parametrize("recon,rs,char", [(1, 1, True), (1, 0, False), (0, 2, True), (0, 1, False)])
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
-def test_step_box_equals_fill_and_solve(H, recon, rs, char, dtype):
+def test_step_box_equals_fill_and_solve(H, scheme, recon, rs, char, dtype):
     gamma = 1.4
     nx, ny, nz = 48, 32, 16
     box = W.lognormal_blast_box(48, gamma=gamma, seed=13, radius_cells=4)[:, :nz, :ny, :nx].copy()
     grouped = _dev(W.box_to_groups(box), dtype)
     G = grouped.shape[0]
-    g = H.ghost_width(H.CTU, recon)
-    dt = O.cfl_dt(box, 1 / 48, gamma, 0.4)
+    g = H.ghost_width(scheme, recon)
+    dt = O.cfl_dt(box, 1 / 48, gamma, 0.4 if scheme == 2 else 0.3)
     dt_dev = torch.tensor([dt], dtype=torch.float64, device="cuda")
     out_box = torch.empty_like(grouped)
     fl_box = torch.empty((G, 3, 3, 5, 16, 16), dtype=dtype, device="cuda")
-    H.step_box(grouped, out_box, (nx, ny, nz), dt_dev, dh=1 / 48, gamma=gamma, scheme=H.CTU, recon=recon,
+    H.step_box(grouped, out_box, (nx, ny, nz), dt_dev, dh=1 / 48, gamma=gamma, scheme=scheme, recon=recon,
                riemann=rs, char=char, flux=fl_box, flux_mid=True)
     ghosted = H.fill_ghosts_periodic(grouped, g, grouped=True, shape=(nx, ny, nz))
     out_ref = torch.empty_like(grouped)
     fl_ref = torch.empty_like(fl_box)
-    H.solve_groups(ghosted, out_ref, fl_ref, dt=dt, dh=1 / 48, gamma=gamma, scheme=H.CTU, recon=recon, riemann=rs,
+    H.solve_groups(ghosted, out_ref, fl_ref, dt=dt, dh=1 / 48, gamma=gamma, scheme=scheme, recon=recon, riemann=rs,
                    char=char, flux_mid=True)
     torch.cuda.synchronize()
     assert torch.equal(out_box, out_ref)
     assert torch.equal(fl_box, fl_ref)
     # and the oracle on the whole periodic box
     src = W.box_to_groups(box) if dtype == torch.float64 else W.box_to_groups(box).astype(np.float32)
-    ref = O.step_box(W.groups_to_box(src.astype(np.float64), nx, ny, nz), dt, 1 / 48, gamma, 2, recon, rs, 1,
+    ref = O.step_box(W.groups_to_box(src.astype(np.float64), nx, ny, nz), dt, 1 / 48, gamma, scheme, recon, rs, 1,
                      O.F_CHAR if char else 0)
     got = W.groups_to_box(out_box.cpu().numpy().astype(np.float64), nx, ny, nz)
     if dtype == torch.float64:
