@@ -166,6 +166,17 @@ int hydro_step_box(const void* box_in, void* box_out, void* flux_out, int nx, in
                    double dt_scale, double dh, double gamma, int scheme, int reconstruction, int riemann, int limiter,
                    int flags, void* stream);
 
+/*
+ * Batched CFL time step (Sec. 4.3): for every segment of the table, the FP64
+ * dt of its `out` state ([count][5][4096] interiors) is written to the
+ * segment's `dt` pointer: dt = cfl * dh / max over the segment's cells of
+ * max_d(|v_d| + c) (dt_scale is not applied).  Bit-identical to
+ * hydro_cfl_dt on each segment alone.  Segments sorted by `first`, covering
+ * [0, n_groups_total).  Two launches for the whole table.
+ */
+int hydro_cfl_dt_batch(const struct hydro_seg* segs, int n_segs, long long n_groups_total, double gamma, double cfl,
+                       int flags, void* stream);
+
 /* Specialization of a batched launch (all segments share it). */
 struct hydro_spec {
   int scheme, reconstruction, riemann, limiter, flags;

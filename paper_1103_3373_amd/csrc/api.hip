@@ -52,6 +52,8 @@ bool overlap(const void* a, size_t na, const void* b, size_t nb) {
 struct Workspace {
   void* plain = nullptr;
   size_t plain_bytes = 0;
+  double* seg_partial = nullptr;  // per-group maxima of hydro_cfl_dt_batch
+  long long seg_partial_n = 0;
   void* vl = nullptr;  // VL half-step scratch (fused path)
   size_t vl_bytes = 0;
   double* partial = nullptr;  // reduction partials (a pool slot or own memory)
@@ -402,6 +404,36 @@ int hydro_cfl_dt(const void* U, int n_groups, double dh, double gamma, double cf
   return 0;
 }
 
+int hydro_cfl_dt_batch(const struct hydro_seg* segs, int n_segs, long long n_groups_total, double gamma, double cfl,
+                       int flags, void* stream) {
+  g_err[0] = 0;
+  if (n_segs < 0 || n_groups_total < 0) return fail(HYDRO_EINVAL, "negative sizes");
+  if (n_groups_total == 0) return 0;
+  if (!segs || n_segs == 0) return fail(HYDRO_EINVAL, "null segment table");
+  if (!(gamma > 1.0) || !(cfl > 0.0)) return fail(HYDRO_EINVAL, "cfl > 0 and gamma > 1 required");
+  if (flags & ~kKnownFlags) return fail(HYDRO_EINVAL, "unknown flag bits");
+  hipStream_t st = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lock(g_mu);
+  DeviceState* ds;
+  if (int rc = device_state(&ds)) return rc;
+  Workspace& w = ds->ws[st];
+  if (w.seg_partial_n < n_groups_total) {
+    if (w.seg_partial) {
+      hipDeviceSynchronize();
+      hipFree(w.seg_partial);
+      w.seg_partial = nullptr;
+      w.seg_partial_n = 0;
+    }
+    hipError_t e = hipMalloc((void**)&w.seg_partial, (size_t)n_groups_total * sizeof(double));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(dt partials)");
+    w.seg_partial_n = n_groups_total;
+  }
+  hipError_t e = hy::launch_seg_dt((const hy::Seg*)segs, n_segs, n_groups_total, gamma, cfl, (flags & HYDRO_F64) ? 1 : 0,
+                                   w.seg_partial, st);
+  if (e != hipSuccess) return hip_fail(e, "batched dt");
+  return 0;
+}
+
 int hydro_conserved_sums(const void* U, int n_groups, double dh, int flags, double* sums_out, void* stream) {
   g_err[0] = 0;
   if (n_groups < 0) return fail(HYDRO_EINVAL, "n_groups < 0");
@@ -599,6 +631,7 @@ void hydro_shutdown(void) {
     for (auto& w : kv.second.ws) {
       if (w.second.plain) hipFree(w.second.plain);
       if (w.second.vl) hipFree(w.second.vl);
+      if (w.second.seg_partial) hipFree(w.second.seg_partial);
       if (w.second.partial && w.second.own_partial) hipFree(w.second.partial);
     }
     if (kv.second.diag) hipFree(kv.second.diag);

@@ -177,6 +177,71 @@ __global__ void __launch_bounds__(256) maxspeed_kernel(const T* __restrict__ U, 
   if (threadIdx.x == 0) partial[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
 }
 
+// Batched time step: one workgroup per group of a segment table computes the
+// group's maximum signal speed (same expression as above); one workgroup per
+// segment then writes dt = cfl * dh / max to the segment's dt pointer.
+template <typename T>
+__global__ void __launch_bounds__(256) seg_maxspeed_kernel(const Seg* __restrict__ segs, int n_segs, double gamma,
+                                                           double* __restrict__ partial) {
+#pragma clang fp contract(off)
+  __shared__ double red[4];
+  const long long gidx = blockIdx.x;
+  int lo = 0, hi = n_segs - 1;  // last segment with first <= gidx
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (segs[mid].first <= gidx) lo = mid;
+    else hi = mid - 1;
+  }
+  const Seg& S = segs[lo];
+  const T* U = reinterpret_cast<const T*>(S.out) + (gidx - S.first) * 5 * 4096;
+  double m = 0.0;
+  for (int q = threadIdx.x; q < 4096; q += blockDim.x) {
+    const T* u = U + q;
+    const double rho = (double)u[0];
+    const double mx = (double)u[4096], my = (double)u[2 * 4096], mz = (double)u[3 * 4096];
+    const double vx = mx / rho, vy = my / rho, vz = mz / rho;
+    const double ke = 0.5 * (mx * vx + my * vy + mz * vz);
+    const double p = (gamma - 1.0) * ((double)u[4 * 4096] - ke);
+    const double cs = __builtin_sqrt(gamma * p / rho);
+    double av = __builtin_fabs(vx);
+    if (__builtin_fabs(vy) > av) av = __builtin_fabs(vy);
+    if (__builtin_fabs(vz) > av) av = __builtin_fabs(vz);
+    const double sp = av + cs;
+    m = sp > m ? sp : m;
+  }
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[gidx] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+__global__ void __launch_bounds__(256) seg_dt_finish_kernel(const Seg* __restrict__ segs,
+                                                            const double* __restrict__ partial, double cfl) {
+#pragma clang fp contract(off)
+  __shared__ double red[4];
+  const Seg& S = segs[blockIdx.x];
+  double m = 0.0;
+  for (long long q = threadIdx.x; q < S.count; q += blockDim.x) m = fmax(m, partial[S.first + q]);
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    *const_cast<double*>(S.dt) = cfl * S.dh / mx;
+  }
+}
+
+hipError_t launch_seg_dt(const Seg* segs, int n_segs, long long n_groups, double gamma, double cfl, int f64,
+                         double* partial, hipStream_t st) {
+  if (n_groups > 2147483647LL) return hipErrorInvalidValue;
+  if (f64) seg_maxspeed_kernel<double><<<dim3((unsigned)n_groups), dim3(256), 0, st>>>(segs, n_segs, gamma, partial);
+  else seg_maxspeed_kernel<float><<<dim3((unsigned)n_groups), dim3(256), 0, st>>>(segs, n_segs, gamma, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  seg_dt_finish_kernel<<<dim3(n_segs), dim3(256), 0, st>>>(segs, partial, cfl);
+  return hipGetLastError();
+}
+
 __global__ void __launch_bounds__(256) dt_finish_kernel(const double* __restrict__ partial, int n, double dh,
                                                         double cfl, double* __restrict__ dt_out) {
 #pragma clang fp contract(off)

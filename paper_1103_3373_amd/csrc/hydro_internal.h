@@ -81,6 +81,8 @@ hipError_t launch_fill_interp(const T* coarse, int cn, const int* layout, long l
 template <typename T>
 hipError_t launch_maxspeed(const T* U, long long n_blocks, long long cells, double gamma, double* partial,
                            int n_partial, hipStream_t st);
+hipError_t launch_seg_dt(const Seg* segs, int n_segs, long long n_groups, double gamma, double cfl, int f64,
+                         double* partial, hipStream_t st);
 hipError_t launch_dt_finish(const double* partial, int n_partial, double dh, double cfl, double* dt_out,
                             hipStream_t st);
 template <typename T>

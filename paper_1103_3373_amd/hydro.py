@@ -24,7 +24,7 @@ F64, CHAR, FLUX_MID, PLAIN, ROE_FB_HLLC, BOX_GROUPED = 0x01, 0x02, 0x04, 0x08, 0
 EXPORTS = (
     "hydro_ghost_width", "hydro_solve_groups", "hydro_cfl_dt", "hydro_conserved_sums",
     "hydro_fill_ghosts_periodic", "hydro_fill_groups_interp", "hydro_solve_batch", "hydro_autotune",
-    "hydro_step_box",
+    "hydro_step_box", "hydro_cfl_dt_batch",
     "hydro_get_diag", "hydro_last_error", "hydro_shutdown",
 )
 
@@ -77,6 +77,8 @@ def lib() -> ctypes.CDLL:
     L.hydro_fill_groups_interp.restype = i
     L.hydro_step_box.argtypes = [P, P, P, i, i, i, P, d, d, d, i, i, i, i, i, P]
     L.hydro_step_box.restype = i
+    L.hydro_cfl_dt_batch.argtypes = [P, i, ll, d, d, i, P]
+    L.hydro_cfl_dt_batch.restype = i
     L.hydro_solve_batch.argtypes = [P, i, ll, ctypes.POINTER(Spec), P]
     L.hydro_solve_batch.restype = i
     L.hydro_autotune.argtypes = [ctypes.POINTER(Spec), i, P]
@@ -220,6 +222,9 @@ def seg_table(segs, device) -> torch.Tensor:
         arr[q] = Seg(i.data_ptr(), o.data_ptr(), 0 if f is None else f.data_ptr(), dtt.data_ptr(), float(sc),
                      float(dh), int(first), int(count), *(box if box else (0, 0, 0)), 1 if box else 0)
     host = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8)
+    if torch.device(device).type == "cuda":
+        # pinned + non-blocking: the host does not wait for the device
+        return host.pin_memory().to(device, non_blocking=True)
     return host.to(device)
 
 
@@ -243,6 +248,12 @@ def step_box(box_in, box_out, shape, dt_dev, *, dh, gamma, scheme, recon, rieman
 def solve_batch(seg_dev: torch.Tensor, n_segs: int, n_groups_total: int, spec: Spec, stream=None):
     _check("hydro_solve_batch", lib().hydro_solve_batch(_ptr(seg_dev), n_segs, int(n_groups_total),
                                                         ctypes.byref(spec), _stream(stream)))
+
+
+def cfl_dt_batch(seg_dev: torch.Tensor, n_segs: int, n_groups_total: int, *, gamma, cfl, f64=False, stream=None):
+    """FP64 dt of every segment's `out` state, written to its dt pointer."""
+    _check("hydro_cfl_dt_batch", lib().hydro_cfl_dt_batch(_ptr(seg_dev), n_segs, int(n_groups_total), float(gamma),
+                                                          float(cfl), F64 if f64 else 0, _stream(stream)))
 
 
 def autotune(spec: Spec, n_groups_hint: int, stream=None) -> int:

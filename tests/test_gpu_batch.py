@@ -195,3 +195,22 @@ def test_step_box_rejects_plain_and_bad_sizes(H):
     H.step_box(ok, y, (16, 16, 16), dt * 0.01, dh=1.0, gamma=1.4, scheme=H.CTU, recon=H.PPM, riemann=H.HLLC)
     torch.cuda.synchronize()
     assert torch.equal(y, ok)  # a uniform state at rest is a steady state
+
+
+def test_cfl_dt_batch_equals_single(H):
+    gamma = 1.4
+    sizes = (32, 48, 16)
+    states, rows, first = [], [], 0
+    for k, n in enumerate(sizes):
+        st = _dev(W.box_to_groups(W.lognormal_blast_box(n, gamma=gamma, seed=30 + k, radius_cells=3)), torch.float32)
+        dt = torch.empty(1, dtype=torch.float64, device="cuda")
+        states.append((st, dt, n))
+        rows.append((st, st, None, dt, 1.0, 1.0 / n, first, st.shape[0]))
+        first += st.shape[0]
+    table = H.seg_table(rows, "cuda")
+    H.cfl_dt_batch(table, len(rows), first, gamma=gamma, cfl=0.4)
+    for st, dt, n in states:
+        single = H.cfl_dt(st, 1.0 / n, gamma, 0.4)
+        torch.cuda.synchronize()
+        assert dt.item() == single.item()
+        assert dt.item() == O.cfl_dt(st.cpu().numpy().astype(np.float64), 1.0 / n, gamma, 0.4)
