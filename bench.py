@@ -60,6 +60,11 @@ def parse():
     p.add_argument("--graph-replays", type=int, default=10, help="replays of a captured two-step HIP graph")
     p.add_argument("--serve", action="store_true",
                    help="run the serving workload instead (Poisson arrivals, continuous batching)")
+    p.add_argument("--precision", action="store_true",
+                   help="run the precision study instead (Kelvin-Helmholtz, FP32 vs FP64 vs oracle)")
+    p.add_argument("--precision-n", type=int, default=64)
+    p.add_argument("--precision-big", type=int, default=512)
+    p.add_argument("--precision-steps", type=int, default=100)
     p.add_argument("--serve-requests", type=int, default=2000)
     p.add_argument("--serve-rate", type=float, default=200.0)
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -116,6 +121,93 @@ def cpu_baseline(ghosted_dev, dt: float, dh: float, gamma: float, budget_s: floa
     return {"value": done * 4096 / el, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{done} of {total} patch groups of the same first-step input (CTU+PPM(char)+HLLC), "
                       f"FP64 oracle (g++ -O2), one thread, {el:.1f} s of oracle time"}
+
+
+def _rel(a, b):
+    a = a.reshape(-1, 5, 4096).transpose(1, 0, 2).reshape(5, -1).astype(np.float64)
+    b = b.reshape(-1, 5, 4096).transpose(1, 0, 2).reshape(5, -1).astype(np.float64)
+    d = np.abs(a - b)
+    return (d.sum(1) / np.abs(b).sum(1)).tolist(), (d.max(1) / np.abs(b).max(1)).tolist()
+
+
+def precision_study(args):
+    """Kelvin-Helmholtz shear layer: the FP32 GPU path against the FP64 GPU
+    path and the FP64 oracle, 100 steps of MHM, VL and CTU (PPM(char) +
+    HLLC) on the same time-step sequence, with FP64 conservation sums; and
+    FP32 against FP64 on the GPU at the large size."""
+    import torch
+    from paper_1103_3373_amd import hydro as H
+    from paper_1103_3373_amd import workloads as W
+
+    gamma = 1.4
+    res = {"metric": "precision study: rel L1 / Linf per conserved variable", "config": {}}
+    n, steps = args.precision_n, args.precision_steps
+    box = W.kelvin_helmholtz_box(n, gamma=gamma)
+    grp = W.box_to_groups(box)
+    import oracle as O
+    for scheme, name, cfl in ((H.MHM, "MHM", 0.3), (H.VL, "VL", 0.3), (H.CTU, "CTU", 0.5)):
+        print(f"[precision] {name} {n}^3 x {steps}", file=sys.stderr, flush=True)
+        kw = dict(dh=1.0 / n, gamma=gamma, scheme=scheme, recon=H.PPM, riemann=H.HLLC, char=True)
+        s64 = torch.from_numpy(grp).cuda()
+        s32 = torch.from_numpy(grp.astype(np.float32)).cuda()
+        o64, o32 = torch.empty_like(s64), torch.empty_like(s32)
+        dt_dev = torch.empty(1, dtype=torch.float64, device="cuda")
+        ref = box.copy()
+        sums0 = H.conserved_sums(s64, 1.0 / n).cpu().numpy()
+        t_or = 0.0
+        for _ in range(steps):
+            dt = O.cfl_dt(ref, 1.0 / n, gamma, cfl)
+            t1 = time.perf_counter()
+            ref = O.step_box(ref, dt, 1.0 / n, gamma, scheme, H.PPM, H.HLLC, H.VANLEER, O.F_CHAR)
+            t_or += time.perf_counter() - t1
+            dt_dev.fill_(dt)
+            H.step_box(s64, o64, (n, n, n), dt_dev, **kw)
+            H.step_box(s32, o32, (n, n, n), dt_dev, **kw)
+            s64, o64 = o64, s64
+            s32, o32 = o32, s32
+        torch.cuda.synchronize()
+        g64, g32 = s64.cpu().numpy(), s32.cpu().numpy()
+        refg = W.box_to_groups(ref)
+        sums64 = H.conserved_sums(s64, 1.0 / n).cpu().numpy()
+        sums32 = H.conserved_sums(s32, 1.0 / n).cpu().numpy()
+        res[name] = {"fp32_vs_oracle": _rel(g32, refg), "fp64_vs_oracle": _rel(g64, refg),
+                     "fp32_vs_fp64": _rel(g32, g64),
+                     "sums_drift_fp64": (np.abs(sums64 - sums0) / np.maximum(np.abs(sums0), 1e-300)).tolist(),
+                     "sums_drift_fp32": (np.abs(sums32 - sums0) / np.maximum(np.abs(sums0), 1e-300)).tolist(),
+                     "oracle_s": t_or}
+    N = args.precision_big
+    if N:
+        print(f"[precision] {N}^3 FP32 vs FP64, CTU", file=sys.stderr, flush=True)
+        big = W.box_to_groups(W.kelvin_helmholtz_box(N, gamma=gamma))
+        kw = dict(dh=1.0 / N, gamma=gamma, scheme=H.CTU, recon=H.PPM, riemann=H.HLLC, char=True)
+        s64 = torch.from_numpy(big).cuda()
+        del big
+        s32 = s64.float()
+        o64, o32 = torch.empty_like(s64), torch.empty_like(s32)
+        dt_dev = torch.empty(1, dtype=torch.float64, device="cuda")
+        sums0 = H.conserved_sums(s64, 1.0 / N).cpu().numpy()
+        for _ in range(steps):
+            H.cfl_dt(s64, 1.0 / N, gamma, 0.5, dt_out=dt_dev)
+            H.step_box(s64, o64, (N, N, N), dt_dev, **kw)
+            H.step_box(s32, o32, (N, N, N), dt_dev, **kw)
+            s64, o64 = o64, s64
+            s32, o32 = o32, s32
+        torch.cuda.synchronize()
+        sums64 = H.conserved_sums(s64, 1.0 / N).cpu().numpy()
+        sums32 = H.conserved_sums(s32, 1.0 / N).cpu().numpy()
+        l1, linf = [], []
+        for v in range(5):
+            a = s32[:, v].double()
+            b = s64[:, v]
+            d = (a - b).abs()
+            l1.append((d.sum() / b.abs().sum()).item())
+            linf.append((d.max() / b.abs().max()).item())
+        res[f"CTU_{N}"] = {"fp32_vs_fp64": (l1, linf),
+                           "sums_drift_fp64": (np.abs(sums64 - sums0) / np.maximum(np.abs(sums0), 1e-300)).tolist(),
+                           "sums_drift_fp32": (np.abs(sums32 - sums0) / np.maximum(np.abs(sums0), 1e-300)).tolist()}
+    res["config"] = {"workload": f"Kelvin-Helmholtz, {n}^3 x {steps} steps (GPU FP32, GPU FP64, oracle) and "
+                                 f"{N}^3 x {steps} (GPU FP32 vs FP64), PPM(char, van Leer) + HLLC, gamma 1.4"}
+    print(json.dumps(res))
 
 
 def serve_bench(args):
@@ -189,6 +281,9 @@ def main():
 
     if args.serve:
         serve_bench(args)
+        return
+    if args.precision:
+        precision_study(args)
         return
 
     n = args.n
