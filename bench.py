@@ -95,7 +95,7 @@ def traffic_from_profile(kernel_src_hash: str):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("fused_ctu.hpp", "hydro_math.hpp", "fused_ctu_f32.hip"):
+    for f in ("fused_ctu.hpp", "fused_common.hpp", "hydro_math.hpp", "fused_ctu_f32.hip"):
         with open(os.path.join(ROOT, "paper_1103_3373_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -126,10 +126,22 @@ def cpu_baseline(ghosted_dev, dt: float, dh: float, gamma: float, budget_s: floa
 
 
 def _rel(a, b):
+    """Per-variable (L1, Linf) of a - b relative to b; the momentum components
+    share the magnitude |m| of b as scale."""
     a = a.reshape(-1, 5, 4096).transpose(1, 0, 2).reshape(5, -1).astype(np.float64)
     b = b.reshape(-1, 5, 4096).transpose(1, 0, 2).reshape(5, -1).astype(np.float64)
     d = np.abs(a - b)
-    return (d.sum(1) / np.abs(b).sum(1)).tolist(), (d.max(1) / np.abs(b).max(1)).tolist()
+    mag = np.sqrt((b[1:4] ** 2).sum(0))
+    s1 = np.array([np.abs(b[0]).sum()] + [mag.sum()] * 3 + [np.abs(b[4]).sum()])
+    si = np.array([np.abs(b[0]).max()] + [mag.max()] * 3 + [np.abs(b[4]).max()])
+    return (d.sum(1) / s1).tolist(), (d.max(1) / si).tolist()
+
+
+def _drift(s, s0, mom):
+    """Conserved-sum drift: relative for mass and energy, relative to the
+    integral of |m| for the momenta."""
+    scale = np.array([abs(s0[0]), mom, mom, mom, abs(s0[4])])
+    return (np.abs(s - s0) / scale).tolist()
 
 
 def precision_study(args):
@@ -156,6 +168,7 @@ def precision_study(args):
         dt_dev = torch.empty(1, dtype=torch.float64, device="cuda")
         ref = box.copy()
         sums0 = H.conserved_sums(s64, 1.0 / n).cpu().numpy()
+        mom = float(np.sqrt((grp[:, 1:4] ** 2).sum(1)).sum()) / n ** 3
         t_or = 0.0
         for _ in range(steps):
             dt = O.cfl_dt(ref, 1.0 / n, gamma, cfl)
@@ -174,8 +187,8 @@ def precision_study(args):
         sums32 = H.conserved_sums(s32, 1.0 / n).cpu().numpy()
         res[name] = {"fp32_vs_oracle": _rel(g32, refg), "fp64_vs_oracle": _rel(g64, refg),
                      "fp32_vs_fp64": _rel(g32, g64),
-                     "sums_drift_fp64": (np.abs(sums64 - sums0) / np.maximum(np.abs(sums0), 1e-300)).tolist(),
-                     "sums_drift_fp32": (np.abs(sums32 - sums0) / np.maximum(np.abs(sums0), 1e-300)).tolist(),
+                     "sums_drift_fp64": _drift(sums64, sums0, mom),
+                     "sums_drift_fp32": _drift(sums32, sums0, mom),
                      "oracle_s": t_or}
     N = args.precision_big
     if N:
@@ -183,6 +196,7 @@ def precision_study(args):
         big = W.box_to_groups(W.kelvin_helmholtz_box(N, gamma=gamma))
         kw = dict(dh=1.0 / N, gamma=gamma, scheme=H.CTU, recon=H.PPM, riemann=H.HLLC, char=True)
         s64 = torch.from_numpy(big).cuda()
+        mom = float(torch.sqrt((s64[:, 1:4] ** 2).sum(1)).sum()) / N ** 3
         del big
         s32 = s64.float()
         o64, o32 = torch.empty_like(s64), torch.empty_like(s32)
@@ -198,15 +212,18 @@ def precision_study(args):
         sums64 = H.conserved_sums(s64, 1.0 / N).cpu().numpy()
         sums32 = H.conserved_sums(s32, 1.0 / N).cpu().numpy()
         l1, linf = [], []
+        mag = torch.sqrt((s64[:, 1:4] ** 2).sum(1))
         for v in range(5):
             a = s32[:, v].double()
             b = s64[:, v]
             d = (a - b).abs()
-            l1.append((d.sum() / b.abs().sum()).item())
-            linf.append((d.max() / b.abs().max()).item())
+            sc = mag if 1 <= v <= 3 else b.abs()
+            l1.append((d.sum() / sc.sum()).item())
+            linf.append((d.max() / sc.max()).item())
+        del mag
         res[f"CTU_{N}"] = {"fp32_vs_fp64": (l1, linf),
-                           "sums_drift_fp64": (np.abs(sums64 - sums0) / np.maximum(np.abs(sums0), 1e-300)).tolist(),
-                           "sums_drift_fp32": (np.abs(sums32 - sums0) / np.maximum(np.abs(sums0), 1e-300)).tolist()}
+                           "sums_drift_fp64": _drift(sums64, sums0, mom),
+                           "sums_drift_fp32": _drift(sums32, sums0, mom)}
     res["config"] = {"workload": f"Kelvin-Helmholtz, {n}^3 x {steps} steps (GPU FP32, GPU FP64, oracle) and "
                                  f"{N}^3 x {steps} (GPU FP32 vs FP64), PPM(char, van Leer) + HLLC, gamma 1.4"}
     print(json.dumps(res))

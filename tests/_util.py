@@ -45,3 +45,21 @@ def scaled_max_err(a, b):
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def field_errors(a, b):
+    """Per-variable (L1, Linf) error of state a against reference b, both
+    grouped [n, 5, 16, 16, 16] or box [5, ...].  Mass and energy errors are
+    relative to the reference's own magnitude; the three momentum components
+    share the reference's momentum magnitude |m| as scale, so a component that
+    is (close to) zero everywhere does not divide by zero."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    ax = 1 if a.ndim == 5 else 0
+    a = np.moveaxis(a, ax, 0).reshape(5, -1)
+    b = np.moveaxis(b, ax, 0).reshape(5, -1)
+    d = np.abs(a - b)
+    mag = np.sqrt((b[1:4] ** 2).sum(0))
+    s1 = np.array([np.abs(b[0]).sum()] + [mag.sum()] * 3 + [np.abs(b[4]).sum()])
+    si = np.array([np.abs(b[0]).max()] + [mag.max()] * 3 + [np.abs(b[4]).max()])
+    return d.sum(1) / np.maximum(s1, 1e-300), d.max(1) / np.maximum(si, 1e-300)
