@@ -37,6 +37,8 @@ METRIC = "cell-updates/s at 256^3 CTU+PPM+HLLC vs plain; HBM roofline %; p50/p99
 # (no ghost-ring recomputation): + - * / sqrt and comparisons = 1, sign ops
 # free.  Regenerate with oracle/count_ops.py.
 OPS_PER_CELL = 2693.9
+# The same count for the other schemes of the 256^3 workload (PPM(char) + HLLC).
+OPS_PER_CELL_SCHEME = {"MHM": 1607.9, "VL": 1775.9, "CTU": OPS_PER_CELL}
 # Non-packed FP32 VALU peak: 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz.
 ALU_PEAK = 256 * 64 * 2 * 2.4e9
 HBM_PEAK = 8.0e12
@@ -49,13 +51,15 @@ BYTES_PER_CELL = 40.0
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=50)
-    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--steps", type=int, default=200)
+    p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--n", type=int, default=256, help="box size (multiple of 16)")
     p.add_argument("--plain-steps", type=int, default=2)
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-plain", action="store_true")
+    p.add_argument("--extra-reps", type=int, default=10,
+                   help="launches per side measurement (groups API, other schemes, copy); 0 skips them")
     p.add_argument("--no-autotune", action="store_true", help="skip the launch-shape autotuner")
     p.add_argument("--graph-replays", type=int, default=10, help="replays of a captured two-step HIP graph")
     p.add_argument("--serve", action="store_true",
@@ -343,6 +347,58 @@ def serve_bench(args):
     print(json.dumps(out))
 
 
+def _time_launches(fn, reps, stream):
+    """Mean ms of `reps` back-to-back calls of fn, HIP events on `stream`."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def side_measurements(args, H, W, state, nxt, dt_dev, n, gamma, dh, stream):
+    """Measurements beside the headline step, outside its timed region:
+    the ghosted-groups API (ghost fill a0 + solve) on the same state, the
+    box-API solve of MHM and VL at the same size, and a device copy for the
+    measured HBM bandwidth."""
+    import torch
+    reps = args.extra_reps
+    cells = n ** 3
+    G = (n // 16) ** 3
+    print(f"[bench] side measurements, {reps} launches each", file=sys.stderr, flush=True)
+    res = {"reps": reps}
+    g = H.ghost_width(H.CTU, H.PPM)
+    ghosted = torch.empty((G, 5, 16 + 2 * g, 16 + 2 * g, 16 + 2 * g), dtype=torch.float32, device=state.device)
+    kw = dict(dh=dh, gamma=gamma, scheme=H.CTU, recon=H.PPM, riemann=H.HLLC, limiter=H.VANLEER, char=True)
+    fill_ms = _time_launches(lambda: H.fill_ghosts_periodic(state, g, grouped=True, shape=(n, n, n), out=ghosted),
+                             reps, stream)
+    dt = float(dt_dev.item())
+    solve_ms = _time_launches(lambda: H.solve_groups(ghosted, nxt, None, dt=dt, **kw), reps, stream)
+    res["groups_api_CTU"] = {"fill_ms": fill_ms, "solve_ms": solve_ms,
+                             "cell_updates_per_s_with_fill": cells / ((fill_ms + solve_ms) * 1e-3),
+                             "cell_updates_per_s_without_fill": cells / (solve_ms * 1e-3),
+                             "algorithmic_bytes_per_cell": 72.0}
+    del ghosted
+    for name, scheme in (("MHM", H.MHM), ("VL", H.VL)):
+        kws = dict(kw, scheme=scheme)
+        ms = _time_launches(lambda: H.step_box(state, nxt, (n, n, n), dt_dev, dt_scale=0.6, **kws), reps, stream)
+        ops = OPS_PER_CELL_SCHEME[name]
+        res[f"box_api_{name}"] = {"solve_ms": ms, "cell_updates_per_s": cells / (ms * 1e-3),
+                                  "ops_per_cell": ops, "alu_frac": ops * cells / (ms * 1e-3) / ALU_PEAK}
+    a = torch.empty(1 << 28, dtype=torch.float32, device=state.device)  # 1 GiB
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    cms = _time_launches(lambda: b.copy_(a), reps, stream)
+    res["copy_GBps"] = 2 * a.numel() * 4 / (cms * 1e-3) / 1e9
+    del a, b
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -457,6 +513,8 @@ def main():
     final_sums = sums.cpu().numpy().tolist()
     assert np.isfinite(final_dt) and final_dt > 0, final_dt
 
+    extras = side_measurements(args, H, W, state, nxt, dt_dev, n, gamma, dh, stream) if args.extra_reps > 0 else None
+
     # Plain per-group FP64 path on the same first-step input (solver only).
     plain = None
     if not args.no_plain and args.plain_steps > 0:
@@ -523,6 +581,7 @@ def main():
                 "algorithmic_GBps": BYTES_PER_CELL * cells / (kern_avg * 1e-3) / 1e9,
                 "frac_of_8TBps": BYTES_PER_CELL * cells / (kern_avg * 1e-3) / HBM_PEAK},
         "plain": plain,
+        "side": extras,
         "cpu_baseline": cpu,
         "autotune_grid": tuned,
         "final_dt": final_dt,

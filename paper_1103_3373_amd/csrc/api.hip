@@ -514,6 +514,21 @@ int hydro_get_diag(struct hydro_diag* out, int reset, void* stream) {
   return 0;
 }
 
+int hydro_set_launch_shape(const struct hydro_spec* spec, int grid, int variant) {
+  g_err[0] = 0;
+  if (!spec) return fail(HYDRO_EINVAL, "null spec");
+  if (int rc = check_options(spec->scheme, spec->reconstruction, spec->riemann, spec->limiter, spec->flags)) return rc;
+  const bool f64 = (spec->flags & HYDRO_F64) != 0;
+  if (grid < 0) return fail(HYDRO_EINVAL, "grid %d < 0", grid);
+  if (variant != 2 && variant != 4) return fail(HYDRO_EINVAL, "variant %d not in {2, 4}", variant);
+  if (f64 && variant != 2) return fail(HYDRO_EINVAL, "FP64 kernels have variant 2 only");
+  const int charlim = (spec->flags & HYDRO_CHAR) ? 1 : 0;
+  std::lock_guard<std::mutex> lock(g_mu);
+  tune_load();
+  g_tune[tune_key(f64, spec->scheme, spec->reconstruction, spec->riemann, charlim)] = Tune{grid, variant};
+  return 0;
+}
+
 int hydro_autotune(const struct hydro_spec* spec, int n_groups_hint, void* stream) {
   g_err[0] = 0;
   if (!spec) return fail(HYDRO_EINVAL, "null spec");

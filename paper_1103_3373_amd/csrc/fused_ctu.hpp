@@ -53,6 +53,10 @@ constexpr int oF1 = oWY + 10 * kSQ;
 constexpr int oG1 = oF1 + 5 * kF1;
 constexpr int oDH = oG1 + 5 * kG1;
 constexpr int kLds = oDH + 5 * kSQ;
+// After the T-typed area: addresses of the ring-corner and outer columns of
+// the current group (column ids 320 .. 467), formed once per group.
+constexpr int kOuterCols = 148;
+constexpr size_t kLdsBytes(size_t elem) { return kLds * elem + kOuterCols * sizeof(void*); }
 // Final in-plane fluxes reuse the slope area (dead after the traces).
 constexpr int kF2 = 17 * 16;          // x faces -1..15, y in 0..15
 constexpr int kG2 = 16 * 17;          // x in 0..15, y faces -1..15
@@ -65,6 +69,7 @@ static_assert(10 * kF2 <= 5 * (kSX + kSY), "F2/G2 alias");
 // some spilling); the autotuner picks per specialization.
 template <typename T, bool PPM, int RS, int WAVES>
 __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T> a) {
+  constexpr int NT = kThreads;
   constexpr int G = PPM ? 3 : 2;
   constexpr int N = 16 + 2 * G;
   extern __shared__ unsigned char smem_raw[];
@@ -79,12 +84,15 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
   T* sDH = sm + oDH;
   T* sF2 = sm + oF2;
   T* sG2 = sm + oG2;
+  const T** sOC = reinterpret_cast<const T**>(smem_raw + kLds * sizeof(T));
 
   const int tid = threadIdx.x;
   const Column<int> col = column_of<G>(tid);
   const int pcol = (col.y + G) * N + (col.x + G);  // primitive plane index
   const int sqc = (col.y + 1) * 18 + (col.x + 1);  // 18x18 square index (cross columns)
   const bool interior = tid < 256;
+  constexpr int nCols = 324 + 4 * (G - 1) * 18;  // columns that feed the primitive plane
+  static_assert(nCols - 320 <= kOuterCols, "outer column table");
   int fails = 0, floors = 0;
 
   Phys<T> ph = make_phys(a);
@@ -108,6 +116,15 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
     // box mode, straight from the periodic grouped box.
     ColumnReader<T, G> rd;
     rd.init(S, lg, col.x, col.y);
+    if (!col.cross) {
+      // Each thread reads back only the slots it writes: no barrier needed.
+      for (int c = tid; c < nCols; c += NT - 320) {
+        const Column<int> oc = column_of<G>(c);
+        ColumnReader<T, G> orr;
+        orr.init(S, lg, oc.x, oc.y);
+        sOC[c - 320] = orr.col;
+      }
+    }
     auto load_cons = [&](int x, int y, int z) -> V5<T> { return rd.load(z); };
     auto zprim = [&](int z) -> V5<T> { return to_frame<2>(prim_of(load_cons(col.x, col.y, z), ph)); };
 
@@ -172,13 +189,20 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
           if (t >= 0) sts5(sDH, kSQ, sqc, from_frame<2>(sub5(h1p, h1m)));
           h1m = h1p;
         }
-      } else if (col.active) {
-        sts5(sP, kP, pcol, prim_of(load_cons(col.x, col.y, t), ph));
+      } else {
+        // Ring corners and outer columns (column ids 320 .. nCols-1), strided
+        // over the threads that own no cross column.
+        for (int c = tid; c < nCols; c += NT - 320) {
+          const Column<int> oc = column_of<G>(c);
+          ColumnReader<T, G> orr = rd;  // z part of the group
+          orr.col = sOC[c - 320];
+          sts5(sP, kP, (oc.y + G) * N + (oc.x + G), prim_of(orr.load(t), ph));
+        }
       }
       __syncthreads();
 
       // ---- B: limited slopes along x and y of plane t ----------------------
-      for (int q = tid; q < nSX + nSY; q += kThreads) {
+      for (int q = tid; q < nSX + nSY; q += NT) {
         if (q < nSX) {
           const int x = q % wSX + x0SX, y = q / wSX - 1;
           const int c = (y + G) * N + (x + G);
@@ -197,7 +221,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
       __syncthreads();
 
       // ---- C: traced x and y face states of plane t (frame order) ----------
-      for (int q = tid; q < 2 * kSQ; q += kThreads) {
+      for (int q = tid; q < 2 * kSQ; q += NT) {
         const int r = q < kSQ ? q : q - kSQ;
         const int x = r % 18 - 1, y = r / 18 - 1;
         const int c = (y + G) * N + (x + G);
@@ -229,7 +253,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
       __syncthreads();
 
       // ---- D: first-set Riemann solves in x and y (lab-order fluxes) -------
-      for (int q = tid; q < kF1 + kG1; q += kThreads) {
+      for (int q = tid; q < kF1 + kG1; q += NT) {
         if (q < kF1) {
           const int i = q % 17 - 1, y = q / 17 - 1;  // face between x = i and i+1
           const int l = (y + 1) * 18 + (i + 1);
@@ -261,7 +285,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
         zcp = cp;
       }
       if (t >= 0 && t <= 15) {
-        for (int q = kThreads - 1 - tid; q < kF2 + kG2; q += kThreads) {
+        for (int q = NT - 1 - tid; q < kF2 + kG2; q += NT) {
           if (q < kF2) {
             const int i = q % 17 - 1, y = q / 17;  // x face between i and i+1, row y
             const int l = (y + 1) * 18 + (i + 1);

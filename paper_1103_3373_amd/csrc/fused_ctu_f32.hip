@@ -6,7 +6,7 @@ namespace hy {
 template <bool PPM, int RS, int WAVES>
 static hipError_t launch_one(const FusedArgs<float>& a, int grid, hipStream_t st) {
   auto k = ctu::ctu_fused_kernel<float, PPM, RS, WAVES>;
-  const size_t shm = (size_t)ctu::kLds * sizeof(float);
+  const size_t shm = ctu::kLdsBytes(sizeof(float));
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);

@@ -6,7 +6,7 @@ namespace hy {
 template <bool PPM, int RS, int WAVES>
 static hipError_t launch_one(const FusedArgs<double>& a, int grid, hipStream_t st) {
   auto k = ctu::ctu_fused_kernel<double, PPM, RS, WAVES>;
-  const size_t shm = (size_t)ctu::kLds * sizeof(double);
+  const size_t shm = ctu::kLdsBytes(sizeof(double));
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);

@@ -24,7 +24,7 @@ F64, CHAR, FLUX_MID, PLAIN, ROE_FB_HLLC, BOX_GROUPED = 0x01, 0x02, 0x04, 0x08, 0
 EXPORTS = (
     "hydro_ghost_width", "hydro_solve_groups", "hydro_cfl_dt", "hydro_conserved_sums",
     "hydro_fill_ghosts_periodic", "hydro_fill_groups_interp", "hydro_solve_batch", "hydro_autotune",
-    "hydro_step_box", "hydro_cfl_dt_batch",
+    "hydro_set_launch_shape", "hydro_step_box", "hydro_cfl_dt_batch",
     "hydro_get_diag", "hydro_last_error", "hydro_shutdown",
 )
 
@@ -83,6 +83,8 @@ def lib() -> ctypes.CDLL:
     L.hydro_solve_batch.restype = i
     L.hydro_autotune.argtypes = [ctypes.POINTER(Spec), i, P]
     L.hydro_autotune.restype = i
+    L.hydro_set_launch_shape.argtypes = [ctypes.POINTER(Spec), i, i]
+    L.hydro_set_launch_shape.restype = i
     L.hydro_get_diag.argtypes = [ctypes.POINTER(Diag), i, P]
     L.hydro_get_diag.restype = i
     L.hydro_last_error.argtypes = []
@@ -258,6 +260,12 @@ def cfl_dt_batch(seg_dev: torch.Tensor, n_segs: int, n_groups_total: int, *, gam
 
 def autotune(spec: Spec, n_groups_hint: int, stream=None) -> int:
     return _check("hydro_autotune", lib().hydro_autotune(ctypes.byref(spec), int(n_groups_hint), _stream(stream)))
+
+
+def set_launch_shape(spec: Spec, grid: int, variant: int) -> None:
+    """Pin the fused kernel's launch shape for spec's specialization
+    (grid 0 = default; variant 2 or 4, see hydro_set_launch_shape)."""
+    _check("hydro_set_launch_shape", lib().hydro_set_launch_shape(ctypes.byref(spec), int(grid), int(variant)))
 
 
 def get_diag(reset=False, stream=None) -> dict:

@@ -83,3 +83,18 @@ def test_product_path_does_not_import_oracle():
             if f.endswith((".py", ".hip", ".h", ".hpp", ".cpp")):
                 src = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in src and "from oracle" not in src and "oracle/" not in src, f
+
+
+def test_set_launch_shape_validation():
+    """Launch-shape pinning validates its arguments on the host (no device call)."""
+    from paper_1103_3373_amd import hydro as H
+    ctu = H.make_spec(H.CTU, H.PPM, H.HLLC, gamma=1.4, char=True)
+    mhm = H.make_spec(H.MHM, H.PPM, H.HLLC, gamma=1.4, char=True)
+    f64 = H.make_spec(H.CTU, H.PPM, H.HLLC, gamma=1.4, char=True, f64=True)
+    for bad in ((ctu, 0, 1), (ctu, 0, 3), (ctu, 0, 5), (ctu, -1, 2), (mhm, 0, 3), (f64, 0, 4)):
+        with pytest.raises(H.HydroError):
+            H.set_launch_shape(*bad)
+    H.set_launch_shape(mhm, 0, 4)
+    H.set_launch_shape(f64, 512, 2)
+    H.set_launch_shape(ctu, 7, 2)
+    H.set_launch_shape(ctu, 0, 4)  # back to the default variant

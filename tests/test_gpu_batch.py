@@ -178,6 +178,40 @@ def test_launch_shape_does_not_change_results(H):
     assert torch.equal(o1, o2)
 
 
+@pytest.mark.parametrize("recon,riemann", [(1, 1), (1, 0), (0, 2)])
+def test_every_launch_variant_gives_identical_results(H, recon, riemann):
+    """CTU FP32 in each register-budget variant and several persistent
+    grid sizes (one group per workgroup, a ragged 7, the default) gives the
+    same bits on the box path and the ghosted-groups path."""
+    gamma = 1.4
+    n = 48
+    box = random_smooth_box(n, gamma, 21 + recon + 2 * riemann, amp=0.3)
+    B = _dev(W.box_to_groups(box), torch.float32)
+    g = H.ghost_width(H.CTU, recon)
+    G = H.fill_ghosts_periodic(_dev(box, torch.float32), g)
+    spec = H.make_spec(H.CTU, recon, riemann, gamma=gamma, char=True)
+    dt = torch.full((1,), 1.5e-3, dtype=torch.float64, device="cuda")
+    kw = dict(dh=1 / n, gamma=gamma, scheme=H.CTU, recon=recon, riemann=riemann, char=True)
+    outs = []
+    try:
+        for variant in (4, 2):
+            for grid in (0, 7, B.shape[0]):
+                H.set_launch_shape(spec, grid, variant)
+                ob = torch.empty_like(B)
+                H.step_box(B, ob, (n, n, n), dt, **kw)
+                og = torch.empty_like(B)
+                H.solve_groups(G, og, None, dt=1.5e-3, **kw)
+                outs.append(((variant, grid), ob, og))
+        torch.cuda.synchronize()
+    finally:
+        H.set_launch_shape(spec, 0, 4)
+    ref_b, ref_g = outs[0][1], outs[0][2]
+    assert torch.equal(ref_b, ref_g)
+    for shape, ob, og in outs[1:]:
+        assert torch.equal(ob, ref_b), shape
+        assert torch.equal(og, ref_g), shape
+
+
 def test_step_box_rejects_plain_and_bad_sizes(H):
     x = torch.zeros((1, 5, 16, 16, 16), device="cuda")
     dt = torch.ones(1, dtype=torch.float64, device="cuda")
