@@ -53,6 +53,14 @@ HY_DEV float vrcp(float a) { return __builtin_amdgcn_rcpf(a); }
 HY_DEV double vrcp(double a) { return 1.0 / a; }
 HY_DEV float vdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 HY_DEV double vdiv(double a, double b) { return a / b; }
+// 1/sqrt(a): one transcendental in FP32 instead of a square root and a
+// reciprocal.  The FP32 kernels use it to share 1/sqrt(rho) and 1/c between
+// the quantities that need them; FP64 keeps the square roots and quotients
+// in the order of their definitions.
+HY_DEV float vrsq(float a) { return __builtin_amdgcn_rsqf(a); }
+HY_DEV double vrsq(double a) { return 1.0 / __builtin_sqrt(a); }
+template <typename T> struct FastMath { static constexpr bool on = false; };
+template <> struct FastMath<float> { static constexpr bool on = true; };
 
 // ---- frames -----------------------------------------------------------------
 template <int D> struct Frame {
@@ -104,6 +112,17 @@ template <typename T> HY_DEV V5<T> flux_of(const V5<T>& W, const Phys<T>& ph) {
 }
 template <typename T> HY_DEV T sound(const V5<T>& W, const Phys<T>& ph) {
   return vsqrt(ph.gamma * W[4] * vrcp(W[0]));
+}
+// Sound speed c and 1/c of a state whose 1/rho is known.
+template <typename T> HY_DEV void sound_pair(const V5<T>& W, T ir, const Phys<T>& ph, T& c, T& ic) {
+  const T c2 = ph.gamma * W[4] * ir;
+  if constexpr (FastMath<T>::on) {
+    ic = vrsq(c2);
+    c = c2 * ic;
+  } else {
+    c = vsqrt(c2);
+    ic = vrcp(c);
+  }
 }
 // Floor on density and pressure of face / half-step states; returns hits.
 template <typename T> HY_DEV int floor_state(V5<T>& W, const Phys<T>& ph) {
@@ -174,8 +193,8 @@ HY_DEV V5<T> slope(const V5<T>& wm, const V5<T>& w0, const V5<T>& wp, const Phys
     return s;
   }
   T ir = vrcp(w0[0]);
-  T c = vsqrt(ph.gamma * w0[4] * ir);
-  T ic = vrcp(c);
+  T c, ic;
+  sound_pair(w0, ir, ph, c, ic);
   T ic2 = ic * ic;
   V5<T> al = char_L(w0, c, ic, ic2, dl);
   V5<T> ar = char_L(w0, c, ic, ic2, dr);
@@ -204,19 +223,18 @@ template <typename T> HY_DEV void ppm_mono(const V5<T>& w, V5<T>& wl, V5<T>& wr)
   const T sixth = T(1) / T(6);
 #pragma unroll
   for (int n = 0; n < 5; ++n) {
-    T a = w[n], l = wl[n], r = wr[n];
-    if ((r - a) * (a - l) <= T(0)) {
-      l = a;
-      r = a;
-    } else {
-      T d = r - l;
-      T t = d * (a - T(0.5) * (l + r));
-      T d2 = d * d * sixth;
-      if (t > d2) l = T(3) * a - T(2) * r;
-      else if (t < -d2) r = T(3) * a - T(2) * l;
-    }
-    wl[n] = l;
-    wr[n] = r;
+    const T a = w[n], l = wl[n], r = wr[n];
+    // The two overshoot cases exclude each other (d2 >= 0), so both
+    // replacements are formed from the unmodified edges and selected.
+    const bool ext = (r - a) * (a - l) <= T(0);
+    const T d = r - l;
+    const T t = d * (a - T(0.5) * (l + r));
+    const T d2 = d * d * sixth;
+    const T a3 = T(3) * a;
+    const T nl = t > d2 ? a3 - T(2) * r : l;
+    const T nr = t < -d2 ? a3 - T(2) * l : r;
+    wl[n] = ext ? a : nl;
+    wr[n] = ext ? a : nr;
   }
 }
 
@@ -246,8 +264,8 @@ HY_DEV void plm_faces(const V5<T>& wm, const V5<T>& w, const V5<T>& wp, const V5
 template <bool PPM, typename T>
 HY_DEV void ctu_trace(const V5<T>& w, V5<T>& fl, V5<T>& fr, const Phys<T>& ph) {
   T ir = vrcp(w[0]);
-  T c = vsqrt(ph.gamma * w[4] * ir);
-  T ic = vrcp(c);
+  T c, ic;
+  sound_pair(w, ir, ph, c, ic);
   T ic2 = ic * ic;
   T s[5];
   s[0] = (w[1] - c) * ph.dtdh;
@@ -274,20 +292,33 @@ HY_DEV void ctu_trace(const V5<T>& w, V5<T>& fl, V5<T>& fr, const Phys<T>& ph) {
     R[n] = fl[n] - T(0.5) * sm * (dw[n] + t6m);
   }
   // Amplitudes of the waves that reach each face, relative to the reference.
+  // A wave moving right (s > 0) reaches the right face only, with the
+  // reference speed sM; one moving left reaches the left face, with sm.  So
+  // each wave has one amplitude, formed with its own reference and routed
+  // to its face; the three middle waves share the speed u and its factors.
   const T third = T(1) / T(3);
   V5<T> aL, aR;
   T sa[5] = {s[0], s[1], s[1], s[1], s[4]};
+  T hk[3], qk[3], gk[3];  // per distinct speed: (sr - s)/2, (sr^2 - s^2)/3, -1 or +1
+  {
+    const T sk[3] = {s[0], s[1], s[4]};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const bool pos = sk[k] > T(0);
+      const T sr = pos ? sM : sm;
+      hk[k] = T(0.5) * (sr - sk[k]);
+      qk[k] = PPM ? (sr * sr - sk[k] * sk[k]) * third : T(0);
+      gk[k] = pos ? T(-1) : T(1);
+    }
+  }
 #pragma unroll
   for (int a = 0; a < 5; ++a) {
+    const int k = a == 0 ? 0 : (a == 4 ? 2 : 1);
     T x6 = PPM ? a6[a] : T(0);
-    T vL = T(0.5) * (sM - sa[a]) * (da[a] - x6);
-    T vR = T(0.5) * (sm - sa[a]) * (da[a] + x6);
-    if (PPM) {
-      vL += (sM * sM - sa[a] * sa[a]) * third * x6;
-      vR += (sm * sm - sa[a] * sa[a]) * third * x6;
-    }
-    aL[a] = sa[a] > T(0) ? vL : T(0);
-    aR[a] = sa[a] < T(0) ? vR : T(0);
+    T v = hk[k] * (PPM ? da[a] + gk[k] * x6 : da[a]);
+    if (PPM) v += qk[k] * x6;
+    aL[a] = sa[a] > T(0) ? v : T(0);
+    aR[a] = sa[a] < T(0) ? v : T(0);
   }
   V5<T> cL = char_R(w, c, ir, aL);
   V5<T> cR = char_R(w, c, ir, aR);
@@ -301,19 +332,39 @@ HY_DEV void ctu_trace(const V5<T>& w, V5<T>& fl, V5<T>& fr, const Phys<T>& ph) {
 // ---- Riemann solvers (frame states in, frame flux out) ----------------------
 template <typename T> struct Roe {
   T u, v, w, H, c2;
+  T rL, rR;  // FP32: 1/sqrt(rho) of the left and right states (unused in FP64)
 };
 template <typename T> HY_DEV Roe<T> roe_avg(const V5<T>& L, const V5<T>& R, T EL, T ER, const Phys<T>& ph) {
-  T sL = vsqrt(L[0]), sR = vsqrt(R[0]);
+  Roe<T> a;
+  T sL, sR, hL, hR;  // sqrt(rho) and (E + p) / sqrt(rho) of each side
+  if constexpr (FastMath<T>::on) {
+    a.rL = vrsq(L[0]);
+    a.rR = vrsq(R[0]);
+    sL = L[0] * a.rL;
+    sR = R[0] * a.rR;
+    hL = (EL + L[4]) * a.rL;
+    hR = (ER + R[4]) * a.rR;
+  } else {
+    a.rL = a.rR = T(0);
+    sL = vsqrt(L[0]);
+    sR = vsqrt(R[0]);
+    hL = vdiv(EL + L[4], sL);
+    hR = vdiv(ER + R[4], sR);
+  }
   T inv = vrcp(sL + sR);
   T wl = sL * inv, wr = sR * inv;
-  Roe<T> a;
   a.u = wl * L[1] + wr * R[1];
   a.v = wl * L[2] + wr * R[2];
   a.w = wl * L[3] + wr * R[3];
   // H = (E + p) / rho; sqrt(rho) * H = (E + p) / sqrt(rho)
-  a.H = (vdiv(EL + L[4], sL) + vdiv(ER + R[4], sR)) * inv;
+  a.H = (hL + hR) * inv;
   a.c2 = ph.gm1 * (a.H - T(0.5) * (a.u * a.u + a.v * a.v + a.w * a.w));
   return a;
+}
+// Sound speed of a state; FP32 takes 1/rho from 1/sqrt(rho).
+template <typename T> HY_DEV T sound_rs(const V5<T>& W, T rs, const Phys<T>& ph) {
+  if constexpr (FastMath<T>::on) return vsqrt(ph.gamma * W[4] * (rs * rs));
+  else return sound(W, ph);
 }
 template <typename T> HY_DEV T total_energy(const V5<T>& W, const Phys<T>& ph) {
   return W[4] * ph.inv_gm1 + T(0.5) * W[0] * (W[1] * W[1] + W[2] * W[2] + W[3] * W[3]);
@@ -324,7 +375,7 @@ HY_DEV V5<T> hlle(const V5<T>& L, const V5<T>& R, const Phys<T>& ph) {
   T EL = total_energy(L, ph), ER = total_energy(R, ph);
   Roe<T> a = roe_avg(L, R, EL, ER, ph);
   T ct = vsqrt(vmax(a.c2, T(0)));
-  T cL = sound(L, ph), cR = sound(R, ph);
+  T cL = sound_rs(L, a.rL, ph), cR = sound_rs(R, a.rR, ph);
   T SL = vmin(L[1] - cL, a.u - ct);
   T SR = vmax(R[1] + cR, a.u + ct);
   T bm = vmin(SL, T(0)), bp = vmax(SR, T(0));
@@ -345,7 +396,7 @@ HY_DEV V5<T> hllc(const V5<T>& L, const V5<T>& R, const Phys<T>& ph) {
   T EL = total_energy(L, ph), ER = total_energy(R, ph);
   Roe<T> a = roe_avg(L, R, EL, ER, ph);
   T ct = vsqrt(vmax(a.c2, T(0)));
-  T cL = sound(L, ph), cR = sound(R, ph);
+  T cL = sound_rs(L, a.rL, ph), cR = sound_rs(R, a.rR, ph);
   T SL = vmin(L[1] - cL, a.u - ct);
   T SR = vmax(R[1] + cR, a.u + ct);
   T mL = L[0] * (SL - L[1]);
@@ -359,6 +410,7 @@ HY_DEV V5<T> hllc(const V5<T>& L, const V5<T>& R, const Phys<T>& ph) {
   T E = left ? EL : ER;
   T S = left ? SL : SR;
   T m = left ? mL : mR;
+  T rs = left ? a.rL : a.rR;
   V5<T> F = flux_of(W, ph);
   if (supL || supR) return F;
   T fac = vdiv(m, S - Ss);
@@ -369,7 +421,8 @@ HY_DEV V5<T> hllc(const V5<T>& L, const V5<T>& R, const Phys<T>& ph) {
   Us[1] = fac * Ss;
   Us[2] = fac * W[2];
   Us[3] = fac * W[3];
-  Us[4] = fac * (vdiv(E, W[0]) + (Ss - W[1]) * (Ss + vdiv(W[4], m)));
+  const T Er = FastMath<T>::on ? E * (rs * rs) : vdiv(E, W[0]);  // E / rho
+  Us[4] = fac * (Er + (Ss - W[1]) * (Ss + vdiv(W[4], m)));
   V5<T> Fs;
 #pragma unroll
   for (int n = 0; n < 5; ++n) Fs[n] = F[n] + S * (Us[n] - U[n]);
