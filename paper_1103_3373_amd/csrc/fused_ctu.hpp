@@ -14,14 +14,19 @@
 //    one and the conservative update are done without any shared memory and
 //    every slope is computed once.
 //  * x and y work of the current plane goes through LDS: primitive plane,
-//    limited slopes, traced face states, first-set fluxes and the
-//    transverse z-flux differences (about 69 KB for FP32, so two
-//    workgroups share a CU).
+//    limited slopes, face states, first-set fluxes and the transverse
+//    z-flux differences (about 78 KB for FP32, so two workgroups share a
+//    CU).  Every per-direction array is laid out in that direction's own
+//    (along, across) coordinates with the components in its frame; the
+//    primitive plane is kept twice, in lab order and transposed in y-frame
+//    order.  An x task and a y task then differ only in base pointers, so
+//    they share one code path and a wavefront that holds both does not
+//    diverge.
 //  * Per plane: A columns (prims, z trace, H1, dH1) | B x/y slopes |
-//    C x/y traces | D x/y Riemann set 1 | E corrected x/y Riemann set 2 and
-//    z correction + z Riemann set 2 | F conservative update and flux store.
-//    Five barriers per plane; the update of plane t-1 completes in plane t
-//    once its upper z flux exists.
+//    (PPM) C1 x/y edges, once per face | C x/y monotonization and traces |
+//    D x/y Riemann set 1 | E corrected x/y Riemann set 2 and z correction
+//    + z Riemann set 2 | F conservative update and flux store.  The update
+//    of plane t-1 completes in plane t once its upper z flux exists.
 //  * The correction of a face state is done by the task that solves that
 //    face, so each corrected state is formed exactly once.
 // Global memory sees only the input (read once per cell), the output and
@@ -36,33 +41,47 @@ namespace ctu {
 using namespace fz;
 
 // LDS layout (elements of T).  Sizes are those of PPM (g = 3); PLM uses a
-// subset of the same layout.
+// subset of the same layout.  For direction d (0 = x, 1 = y) a cell has the
+// along coordinate a and the across coordinate b: (a, b) = (x, y) for x and
+// (y, x) for y.
 constexpr int kNmax = 22;
-constexpr int kP = kNmax * kNmax;   // primitive plane, full padded square
-constexpr int kSX = 20 * 18;        // x slopes: x in -2..17, y in -1..16
-constexpr int kSY = 18 * 20;        // y slopes: x in -1..16, y in -2..17
-constexpr int kSQ = 18 * 18;        // x,y in -1..16
-constexpr int kF1 = 17 * 18;        // x faces -1..15 (i+1/2), y in -1..16
-constexpr int kG1 = 18 * 17;        // x in -1..16, y faces -1..15
-constexpr int oP = 0;
-constexpr int oSX = oP + 5 * kP;
-constexpr int oSY = oSX + 5 * kSX;
-constexpr int oWX = oSY + 5 * kSY;    // [2][5][kSQ]: 0 = left face, 1 = right face
-constexpr int oWY = oWX + 10 * kSQ;
-constexpr int oF1 = oWY + 10 * kSQ;
-constexpr int oG1 = oF1 + 5 * kF1;
-constexpr int oDH = oG1 + 5 * kG1;
+constexpr int kP = kNmax * kNmax;    // primitive plane, full padded square
+constexpr int kS = 18 * 20;          // slopes: b in -1..16, a in -2..17
+constexpr int kSQ = 18 * 18;         // b, a in -1..16 (and the lab 18x18 square)
+constexpr int kF1 = 18 * 17;         // first-set fluxes: b in -1..16, faces a+1/2, a in -1..15
+constexpr int kF2 = 16 * 17;         // final fluxes: b in 0..15, faces a+1/2, a in -1..15
+constexpr int oP = 0;                // [5][kP] lab order, (y+G) N + (x+G)
+constexpr int oQ = oP + 5 * kP;      // [5][kP] y frame, transposed: (x+G) N + (y+G)
+constexpr int oS = oQ + 5 * kP;      // [2][5][kS] frame of d, (b+1) 20 + (a+2)
+constexpr int oW = oS + 10 * kS;     // [2][2][5][kSQ] frame of d, (b+1) 18 + (a+1); side 0 = left face
+constexpr int oF1 = oW + 20 * kSQ;   // [2][5][kF1] frame of the OTHER direction, (b+1) 17 + (a+1)
+constexpr int oDH = oF1 + 10 * kF1;  // [5][kSQ] lab order, (y+1) 18 + (x+1)
 constexpr int kLds = oDH + 5 * kSQ;
+constexpr int oF2 = oS;              // [2][5][kF2] frame of d, b 17 + (a+1): slopes are dead by then
+static_assert(10 * kF2 <= 10 * kS, "final fluxes alias the slopes");
 // After the T-typed area: addresses of the ring-corner and outer columns of
 // the current group (column ids 320 .. 467), formed once per group.
 constexpr int kOuterCols = 148;
 constexpr size_t kLdsBytes(size_t elem) { return kLds * elem + kOuterCols * sizeof(void*); }
-// Final in-plane fluxes reuse the slope area (dead after the traces).
-constexpr int kF2 = 17 * 16;          // x faces -1..15, y in 0..15
-constexpr int kG2 = 16 * 17;          // x in 0..15, y faces -1..15
-constexpr int oF2 = oSX;
-constexpr int oG2 = oSX + 5 * kF2;
-static_assert(10 * kF2 <= 5 * (kSX + kSY), "F2/G2 alias");
+
+// Frame changes for a direction d known per lane (0 = x, whose frame is the
+// lab order, 1 = y, whose frame is (v, w, u)).
+template <typename T> HY_DEV V5<T> to_frame_d(const V5<T>& v, bool d) {
+  V5<T> r;
+  r[0] = v[0]; r[1] = d ? v[2] : v[1]; r[2] = d ? v[3] : v[2]; r[3] = d ? v[1] : v[3]; r[4] = v[4];
+  return r;
+}
+template <typename T> HY_DEV V5<T> from_frame_d(const V5<T>& v, bool d) {
+  V5<T> r;
+  r[0] = v[0]; r[1] = d ? v[3] : v[1]; r[2] = d ? v[1] : v[2]; r[3] = d ? v[2] : v[3]; r[4] = v[4];
+  return r;
+}
+// Frame of d -> frame of the other direction.
+template <typename T> HY_DEV V5<T> other_frame_d(const V5<T>& v, bool d) {
+  V5<T> r;
+  r[0] = v[0]; r[1] = d ? v[3] : v[2]; r[2] = d ? v[1] : v[3]; r[3] = d ? v[2] : v[1]; r[4] = v[4];
+  return r;
+}
 
 // WAVES = minimum waves per SIMD the register allocation must allow: 2 gives
 // one workgroup per CU without spills, 4 gives two workgroups per CU (with
@@ -75,20 +94,18 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
   extern __shared__ unsigned char smem_raw[];
   T* sm = reinterpret_cast<T*>(smem_raw);
   T* sP = sm + oP;
-  T* sSX = sm + oSX;
-  T* sSY = sm + oSY;
-  T* sWX = sm + oWX;
-  T* sWY = sm + oWY;
+  T* sQ = sm + oQ;
+  T* sS = sm + oS;
+  T* sW = sm + oW;
   T* sF1 = sm + oF1;
-  T* sG1 = sm + oG1;
   T* sDH = sm + oDH;
   T* sF2 = sm + oF2;
-  T* sG2 = sm + oG2;
   const T** sOC = reinterpret_cast<const T**>(smem_raw + kLds * sizeof(T));
 
   const int tid = threadIdx.x;
   const Column<int> col = column_of<G>(tid);
-  const int pcol = (col.y + G) * N + (col.x + G);  // primitive plane index
+  const int pcol = (col.y + G) * N + (col.x + G);  // primitive plane index, lab
+  const int qcol = (col.x + G) * N + (col.y + G);  // the same cell in the transposed plane
   const int sqc = (col.y + 1) * 18 + (col.x + 1);  // 18x18 square index (cross columns)
   const bool interior = tid < 256;
   constexpr int nCols = 324 + 4 * (G - 1) * 18;  // columns that feed the primitive plane
@@ -97,11 +114,11 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
 
   Phys<T> ph = make_phys(a);
 
-  // Slope task counts (PLM needs slopes of the traced cells only).
-  constexpr int wSX = PPM ? 20 : 18, x0SX = PPM ? -2 : -1;
-  constexpr int nSX = wSX * 18;
-  constexpr int hSY = PPM ? 20 : 18, y0SY = PPM ? -2 : -1;
-  constexpr int nSY = 18 * hSY;
+  // Task counts per direction.  Slopes: PPM needs a in -2..17 (edges of the
+  // traced cells), PLM a in -1..16.  PPM edges: faces a+1/2, a in -2..16.
+  constexpr int wS = PPM ? 20 : 18, a0S = PPM ? -2 : -1;
+  constexpr int nS = wS * 18;
+  constexpr int nE = 19 * 18;
 
   int seg = 0;
   for (long long grp = blockIdx.x; grp < a.n_groups; grp += gridDim.x) {
@@ -125,8 +142,8 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
         sOC[c - 320] = orr.col;
       }
     }
-    auto load_cons = [&](int x, int y, int z) -> V5<T> { return rd.load(z); };
-    auto zprim = [&](int z) -> V5<T> { return to_frame<2>(prim_of(load_cons(col.x, col.y, z), ph)); };
+    auto load_cons = [&](int z) -> V5<T> { return rd.load(z); };
+    auto zprim = [&](int z) -> V5<T> { return to_frame<2>(prim_of(load_cons(z), ph)); };
 
     // Register state of a cross column (frame z unless noted):
     V5<T> w0, w1, w2;   // W(t), W(t+1), W(t+2)   (PLM: w0, w1)
@@ -166,7 +183,9 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
       // ---- A: columns: primitive plane t; trace plane t+1; H1(t+1/2) -------
       V5<T> nzm, nzp;  // traced states of plane t+1
       if (col.cross) {
-        sts5(sP, kP, pcol, from_frame<2>(w0));
+        const V5<T> wl = from_frame<2>(w0);
+        sts5(sP, kP, pcol, wl);
+        sts5(sQ, kP, qcol, to_frame<1>(wl));
         if (t <= 15) {
           if (PPM) {
             V5<T> w3 = zprim(t + 3);
@@ -196,76 +215,80 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
           const Column<int> oc = column_of<G>(c);
           ColumnReader<T, G> orr = rd;  // z part of the group
           orr.col = sOC[c - 320];
-          sts5(sP, kP, (oc.y + G) * N + (oc.x + G), prim_of(orr.load(t), ph));
+          const V5<T> wl = prim_of(orr.load(t), ph);
+          sts5(sP, kP, (oc.y + G) * N + (oc.x + G), wl);
+          sts5(sQ, kP, (oc.x + G) * N + (oc.y + G), to_frame<1>(wl));
         }
       }
       __syncthreads();
 
       // ---- B: limited slopes along x and y of plane t ----------------------
-      for (int q = tid; q < nSX + nSY; q += NT) {
-        if (q < nSX) {
-          const int x = q % wSX + x0SX, y = q / wSX - 1;
-          const int c = (y + G) * N + (x + G);
-          V5<T> s = slope(to_frame<0>(lds5(sP, kP, c - 1)), to_frame<0>(lds5(sP, kP, c)),
-                          to_frame<0>(lds5(sP, kP, c + 1)), ph);
-          sts5(sSX, kSX, (y + 1) * 20 + (x + 2), s);
-        } else {
-          const int r = q - nSX;
-          const int x = r % 18 - 1, y = r / 18 + y0SY;
-          const int c = (y + G) * N + (x + G);
-          V5<T> s = slope(to_frame<1>(lds5(sP, kP, c - N)), to_frame<1>(lds5(sP, kP, c)),
-                          to_frame<1>(lds5(sP, kP, c + N)), ph);
-          sts5(sSY, kSY, (y + 2) * 18 + (x + 1), s);
-        }
+      for (int q = tid; q < 2 * nS; q += NT) {
+        const bool d = q >= nS;
+        const int r = d ? q - nS : q;
+        const int aa = r % wS + a0S, b = r / wS - 1;
+        const T* pl = d ? sQ : sP;
+        const int c = (b + G) * N + (aa + G);
+        V5<T> s = slope(lds5(pl, kP, c - 1), lds5(pl, kP, c), lds5(pl, kP, c + 1), ph);
+        sts5(sS + (d ? 5 * kS : 0), kS, (b + 1) * 20 + (aa + 2), s);
       }
       __syncthreads();
 
-      // ---- C: traced x and y face states of plane t (frame order) ----------
+      // ---- C1 (PPM): x and y edge values, once per face --------------------
+      if (PPM) {
+        for (int q = tid; q < 2 * nE; q += NT) {
+          const bool d = q >= nE;
+          const int r = d ? q - nE : q;
+          const int aa = r % 19 - 2, b = r / 19 - 1;  // face between cells aa and aa+1
+          const T* pl = d ? sQ : sP;
+          const T* ss = sS + (d ? 5 * kS : 0);
+          const int c = (b + G) * N + (aa + G);
+          const int si = (b + 1) * 20 + (aa + 2);
+          V5<T> e = ppm_edge(lds5(pl, kP, c), lds5(pl, kP, c + 1), lds5(ss, kS, si), lds5(ss, kS, si + 1));
+          T* w = sW + (d ? 10 * kSQ : 0);
+          const int wi = (b + 1) * 18 + (aa + 1);  // cell aa
+          if (aa >= -1) sts5(w + 5 * kSQ, kSQ, wi, e);  // right face of cell aa
+          if (aa <= 15) sts5(w, kSQ, wi + 1, e);        // left face of cell aa+1
+        }
+        __syncthreads();
+      }
+
+      // ---- C: traced x and y face states of plane t (frame of d) -----------
       for (int q = tid; q < 2 * kSQ; q += NT) {
-        const int r = q < kSQ ? q : q - kSQ;
-        const int x = r % 18 - 1, y = r / 18 - 1;
-        const int c = (y + G) * N + (x + G);
+        const bool d = q >= kSQ;
+        const int r = d ? q - kSQ : q;
+        const int aa = r % 18 - 1, b = r / 18 - 1;
+        const T* pl = d ? sQ : sP;
+        const int c = (b + G) * N + (aa + G);
+        T* w = sW + (d ? 10 * kSQ : 0);
+        const V5<T> wc = lds5(pl, kP, c);
         V5<T> fl, fr;
-        if (q < kSQ) {
-          V5<T> wm = to_frame<0>(lds5(sP, kP, c - 1)), w = to_frame<0>(lds5(sP, kP, c)),
-                wp = to_frame<0>(lds5(sP, kP, c + 1));
-          const int si = (y + 1) * 20 + (x + 2);
-          V5<T> s0 = lds5(sSX, kSX, si);
-          V5<T> smn = PPM ? lds5(sSX, kSX, si - 1) : s0, spl = PPM ? lds5(sSX, kSX, si + 1) : s0;
-          face_values<PPM>(wm, w, wp, smn, s0, spl, ph, fl, fr);
-          ctu_trace<PPM>(w, fl, fr, ph);
-          floors += floor_state(fl, ph) + floor_state(fr, ph);
-          sts5(sWX, kSQ, r, fl);
-          sts5(sWX + 5 * kSQ, kSQ, r, fr);
+        if (PPM) {
+          fl = lds5(w, kSQ, r);
+          fr = lds5(w + 5 * kSQ, kSQ, r);
+          ppm_mono(wc, fl, fr);
         } else {
-          V5<T> wm = to_frame<1>(lds5(sP, kP, c - N)), w = to_frame<1>(lds5(sP, kP, c)),
-                wp = to_frame<1>(lds5(sP, kP, c + N));
-          const int si = (y + 2) * 18 + (x + 1);
-          V5<T> s0 = lds5(sSY, kSY, si);
-          V5<T> smn = PPM ? lds5(sSY, kSY, si - 18) : s0, spl = PPM ? lds5(sSY, kSY, si + 18) : s0;
-          face_values<PPM>(wm, w, wp, smn, s0, spl, ph, fl, fr);
-          ctu_trace<PPM>(w, fl, fr, ph);
-          floors += floor_state(fl, ph) + floor_state(fr, ph);
-          sts5(sWY, kSQ, r, fl);
-          sts5(sWY + 5 * kSQ, kSQ, r, fr);
+          const T* ss = sS + (d ? 5 * kS : 0);
+          plm_faces(lds5(pl, kP, c - 1), wc, lds5(pl, kP, c + 1), lds5(ss, kS, (b + 1) * 20 + (aa + 2)), ph, fl,
+                    fr);
         }
+        ctu_trace<PPM>(wc, fl, fr, ph);
+        floors += floor_state(fl, ph) + floor_state(fr, ph);
+        sts5(w, kSQ, r, fl);
+        sts5(w + 5 * kSQ, kSQ, r, fr);
       }
       __syncthreads();
 
-      // ---- D: first-set Riemann solves in x and y (lab-order fluxes) -------
-      for (int q = tid; q < kF1 + kG1; q += NT) {
-        if (q < kF1) {
-          const int i = q % 17 - 1, y = q / 17 - 1;  // face between x = i and i+1
-          const int l = (y + 1) * 18 + (i + 1);
-          V5<T> F = riemann<RS>(lds5(sWX + 5 * kSQ, kSQ, l), lds5(sWX, kSQ, l + 1), ph, &fails);
-          sts5(sF1, kF1, q, from_frame<0>(F));
-        } else {
-          const int r = q - kF1;
-          const int x = r % 18 - 1, j = r / 18 - 1;  // face between y = j and j+1
-          const int l = (j + 1) * 18 + (x + 1);
-          V5<T> F = riemann<RS>(lds5(sWY + 5 * kSQ, kSQ, l), lds5(sWY, kSQ, l + 18), ph, &fails);
-          sts5(sG1, kG1, r, from_frame<1>(F));
-        }
+      // ---- D: first-set Riemann solves in x and y, stored in the other
+      //         direction's frame (where they are used) ----------------------
+      for (int q = tid; q < 2 * kF1; q += NT) {
+        const bool d = q >= kF1;
+        const int r = d ? q - kF1 : q;
+        const int i = r % 17 - 1, b = r / 17 - 1;  // face between cells i and i+1 of row b
+        const T* w = sW + (d ? 10 * kSQ : 0);
+        const int l = (b + 1) * 18 + (i + 1);
+        V5<T> F = riemann<RS>(lds5(w + 5 * kSQ, kSQ, l), lds5(w, kSQ, l + 1), ph, &fails);
+        sts5(sF1 + (d ? 5 * kF1 : 0), kF1, r, other_frame_d(F, d));
       }
       __syncthreads();
 
@@ -274,44 +297,40 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
       V5<T> hn;
       if (interior) {
         const int x = col.x, y = col.y;
+        // x fluxes (stored in the y frame) at x -+ 1/2, y fluxes (stored in
+        // the lab order) at y -+ 1/2.
         V5<T> dF = sub5(lds5(sF1, kF1, (y + 1) * 17 + x + 1), lds5(sF1, kF1, (y + 1) * 17 + x));
-        V5<T> dG = sub5(lds5(sG1, kG1, (y + 1) * 18 + x + 1), lds5(sG1, kG1, y * 18 + x + 1));
+        V5<T> dG = sub5(lds5(sF1 + 5 * kF1, kF1, (x + 1) * 17 + y + 1), lds5(sF1 + 5 * kF1, kF1, (x + 1) * 17 + y));
+        const V5<T> fz_ = to_frame<2>(from_frame<1>(dF)), gz_ = to_frame<2>(dG);
         V5<T> d;
 #pragma unroll
-        for (int n = 0; n < 5; ++n) d[n] = dF[n] + dG[n];
-        d = to_frame<2>(d);
+        for (int n = 0; n < 5; ++n) d[n] = fz_[n] + gz_[n];
         V5<T> cm = correct(ztm, d, ph, floors), cp = correct(ztp, d, ph, floors);
         if (t >= 0) hn = from_frame<2>(riemann<RS>(zcp, cm, ph, &fails));  // H(t-1/2)
         zcp = cp;
       }
       if (t >= 0 && t <= 15) {
-        for (int q = NT - 1 - tid; q < kF2 + kG2; q += NT) {
-          if (q < kF2) {
-            const int i = q % 17 - 1, y = q / 17;  // x face between i and i+1, row y
-            const int l = (y + 1) * 18 + (i + 1);
-            V5<T> dl, dr;
-            V5<T> gl = sub5(lds5(sG1, kG1, (y + 1) * 18 + i + 1), lds5(sG1, kG1, y * 18 + i + 1));
-            V5<T> gr = sub5(lds5(sG1, kG1, (y + 1) * 18 + i + 2), lds5(sG1, kG1, y * 18 + i + 2));
-            V5<T> hl = lds5(sDH, kSQ, l), hr = lds5(sDH, kSQ, l + 1);
+        for (int q = NT - 1 - tid; q < 2 * kF2; q += NT) {
+          const bool d = q >= kF2;
+          const int r = d ? q - kF2 : q;
+          const int i = r % 17 - 1, b = r / 17;  // face between cells i and i+1 of row b
+          const T* w = sW + (d ? 10 * kSQ : 0);
+          // The other direction's first-set fluxes, already in this frame:
+          // its rows are this direction's cells, its faces run along b.
+          const T* fo = sF1 + (d ? 0 : 5 * kF1);
+          V5<T> ol = sub5(lds5(fo, kF1, (i + 1) * 17 + b + 1), lds5(fo, kF1, (i + 1) * 17 + b));
+          V5<T> orr = sub5(lds5(fo, kF1, (i + 2) * 17 + b + 1), lds5(fo, kF1, (i + 2) * 17 + b));
+          // z-flux differences of the two cells, lab order -> this frame.
+          const int hl = d ? (i + 1) * 18 + (b + 1) : (b + 1) * 18 + (i + 1);
+          const int hr = hl + (d ? 18 : 1);
+          const V5<T> Hl = to_frame_d(lds5(sDH, kSQ, hl), d), Hr = to_frame_d(lds5(sDH, kSQ, hr), d);
+          V5<T> dl, dr;
 #pragma unroll
-            for (int n = 0; n < 5; ++n) { dl[n] = gl[n] + hl[n]; dr[n] = gr[n] + hr[n]; }
-            V5<T> L = correct(lds5(sWX + 5 * kSQ, kSQ, l), to_frame<0>(dl), ph, floors);
-            V5<T> R = correct(lds5(sWX, kSQ, l + 1), to_frame<0>(dr), ph, floors);
-            sts5(sF2, kF2, q, from_frame<0>(riemann<RS>(L, R, ph, &fails)));
-          } else {
-            const int r = q - kF2;
-            const int x = r % 16, j = r / 16 - 1;  // y face between j and j+1, column x
-            const int l = (j + 1) * 18 + (x + 1);
-            V5<T> dl, dr;
-            V5<T> fl_ = sub5(lds5(sF1, kF1, (j + 1) * 17 + x + 1), lds5(sF1, kF1, (j + 1) * 17 + x));
-            V5<T> fr_ = sub5(lds5(sF1, kF1, (j + 2) * 17 + x + 1), lds5(sF1, kF1, (j + 2) * 17 + x));
-            V5<T> hl = lds5(sDH, kSQ, l), hr = lds5(sDH, kSQ, l + 18);
-#pragma unroll
-            for (int n = 0; n < 5; ++n) { dl[n] = hl[n] + fl_[n]; dr[n] = hr[n] + fr_[n]; }
-            V5<T> L = correct(lds5(sWY + 5 * kSQ, kSQ, l), to_frame<1>(dl), ph, floors);
-            V5<T> R = correct(lds5(sWY, kSQ, l + 18), to_frame<1>(dr), ph, floors);
-            sts5(sG2, kG2, r, from_frame<1>(riemann<RS>(L, R, ph, &fails)));
-          }
+          for (int n = 0; n < 5; ++n) { dl[n] = ol[n] + Hl[n]; dr[n] = orr[n] + Hr[n]; }
+          const int l = (b + 1) * 18 + (i + 1);
+          V5<T> L = correct(lds5(w + 5 * kSQ, kSQ, l), dl, ph, floors);
+          V5<T> R = correct(lds5(w, kSQ, l + 1), dr, ph, floors);
+          sts5(sF2 + (d ? 5 * kF2 : 0), kF2, r, riemann<RS>(L, R, ph, &fails));
         }
       }
       __syncthreads();
@@ -321,7 +340,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
       if (interior) {
         const int x = col.x, y = col.y;
         if (t >= 1) {
-          V5<T> u = load_cons(x, y, t - 1);
+          V5<T> u = load_cons(t - 1);
           const int o = ((t - 1) * 16 + y) * 16 + x;
 #pragma unroll
           for (int n = 0; n < 5; ++n) O[n * 4096 + o] = u[n] - ph.dtdh * (accp[n] + (hn[n] - hprev[n]));
@@ -329,7 +348,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
         if (t >= 0) hprev = hn;
         if (t >= 0 && t <= 15) {
           V5<T> fx = sub5(lds5(sF2, kF2, y * 17 + x + 1), lds5(sF2, kF2, y * 17 + x));
-          V5<T> gy = sub5(lds5(sG2, kG2, (y + 1) * 16 + x), lds5(sG2, kG2, y * 16 + x));
+          V5<T> gy = from_frame<1>(sub5(lds5(sF2 + 5 * kF2, kF2, x * 17 + y + 1), lds5(sF2 + 5 * kF2, kF2, x * 17 + y)));
 #pragma unroll
           for (int n = 0; n < 5; ++n) accp[n] = fx[n] + gy[n];
         }
@@ -343,11 +362,12 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
       } else if (FO && t >= 0 && t <= 15) {
         const int q = tid - 256;
         if (q < 2 * a.nf * 16) {
-          const int d = q / (a.nf * 16), f = (q / 16) % a.nf, s = q % 16;
+          const bool d = q >= a.nf * 16;
+          const int f = (q / 16) % a.nf, s = q % 16;
           const int fi = f == 0 ? -1 : (f == 1 ? 15 : 7);  // face index of offsets 0, 16, 8
-          V5<T> v = d == 0 ? lds5(sF2, kF2, s * 17 + fi + 1) : lds5(sG2, kG2, (fi + 1) * 16 + s);
+          const V5<T> v = from_frame_d(lds5(sF2 + (d ? 5 * kF2 : 0), kF2, s * 17 + fi + 1), d);
 #pragma unroll
-          for (int n = 0; n < 5; ++n) FO[((d * a.nf + f) * 5 + n) * 256 + t * 16 + s] = v[n];
+          for (int n = 0; n < 5; ++n) FO[(((d ? 1 : 0) * a.nf + f) * 5 + n) * 256 + t * 16 + s] = v[n];
         }
       }
       if (col.cross) {
