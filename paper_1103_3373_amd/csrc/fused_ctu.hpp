@@ -151,8 +151,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
     V5<T> ztm, ztp;     // traced states of plane t
     V5<T> h1m;          // H1(t-1/2)
     V5<T> zcp;          // corrected right state of plane t-1
-    V5<T> hprev;        // final H below the plane being updated (lab)
-    V5<T> accp;         // in-plane flux differences of the plane being updated (lab)
+    V5<T> acc;          // flux differences of the plane being updated, all but its upper z face (lab)
 
     // ---- prologue: window and traced states of plane -1 -------------------
     if (col.cross) {
@@ -343,14 +342,13 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
           V5<T> u = load_cons(t - 1);
           const int o = ((t - 1) * 16 + y) * 16 + x;
 #pragma unroll
-          for (int n = 0; n < 5; ++n) O[n * 4096 + o] = u[n] - ph.dtdh * (accp[n] + (hn[n] - hprev[n]));
+          for (int n = 0; n < 5; ++n) O[n * 4096 + o] = u[n] - ph.dtdh * (acc[n] + hn[n]);
         }
-        if (t >= 0) hprev = hn;
         if (t >= 0 && t <= 15) {
           V5<T> fx = sub5(lds5(sF2, kF2, y * 17 + x + 1), lds5(sF2, kF2, y * 17 + x));
           V5<T> gy = from_frame<1>(sub5(lds5(sF2 + 5 * kF2, kF2, x * 17 + y + 1), lds5(sF2 + 5 * kF2, kF2, x * 17 + y)));
 #pragma unroll
-          for (int n = 0; n < 5; ++n) accp[n] = fx[n] + gy[n];
+          for (int n = 0; n < 5; ++n) acc[n] = (fx[n] + gy[n]) - hn[n];  // hn is the lower z face of plane t
         }
         if (FO) {
           const int f = (t == 0) ? 0 : (t == 16 ? 1 : (t == 8 && a.nf == 3 ? 2 : -1));
