@@ -60,9 +60,18 @@ constexpr int kLds = oDH + 5 * kSQ;
 constexpr int oF2 = oS;              // [2][5][kF2] frame of d, b 17 + (a+1): slopes are dead by then
 static_assert(10 * kF2 <= 10 * kS, "final fluxes alias the slopes");
 // After the T-typed area: addresses of the ring-corner and outer columns of
-// the current group (column ids 320 .. 467), formed once per group.
+// the current group (column ids 320 .. 467), formed once per group, then the
+// workgroup's two diagnostic counters (Roe fallbacks, floor hits).
 constexpr int kOuterCols = 148;
-constexpr size_t kLdsBytes(size_t elem) { return kLds * elem + kOuterCols * sizeof(void*); }
+constexpr size_t kLdsBytes(size_t elem) { return kLds * elem + kOuterCols * sizeof(void*) + 2 * sizeof(unsigned); }
+
+// Diagnostic counts go straight to LDS counters (rare events), so no
+// register carries them through the plane loop.
+struct Tally {
+  unsigned* c;  // [0] Roe fallbacks, [1] floor hits
+  HY_DEV void fails(int v) const { if (v) atomicAdd(&c[0], (unsigned)v); }
+  HY_DEV void floors(int v) const { if (v) atomicAdd(&c[1], (unsigned)v); }
+};
 
 // Frame changes for a direction d known per lane (0 = x, whose frame is the
 // lab order, 1 = y, whose frame is (v, w, u)).
@@ -101,6 +110,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
   T* sDH = sm + oDH;
   T* sF2 = sm + oF2;
   const T** sOC = reinterpret_cast<const T**>(smem_raw + kLds * sizeof(T));
+  const Tally tally{reinterpret_cast<unsigned*>(smem_raw + kLds * sizeof(T) + kOuterCols * sizeof(void*))};
 
   const int tid = threadIdx.x;
   const Column<int> col = column_of<G>(tid);
@@ -110,7 +120,8 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
   const bool interior = tid < 256;
   constexpr int nCols = 324 + 4 * (G - 1) * 18;  // columns that feed the primitive plane
   static_assert(nCols - 320 <= kOuterCols, "outer column table");
-  int fails = 0, floors = 0;
+  if (tid < 2) tally.c[tid] = 0u;
+  __syncthreads();
 
   Phys<T> ph = make_phys(a);
 
@@ -175,7 +186,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
         plm_faces(wb, w0, w1, sb, ph, ztm, ztp);
         ctu_trace<false>(w0, ztm, ztp, ph);
       }
-      floors += floor_state(ztm, ph) + floor_state(ztp, ph);
+      tally.floors(floor_state(ztm, ph) + floor_state(ztp, ph));
     }
 
     for (int t = -1; t <= 16; ++t) {
@@ -202,8 +213,10 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
             ctu_trace<false>(w1, nzm, nzp, ph);
             w0 = w1; w1 = w3;
           }
-          floors += floor_state(nzm, ph) + floor_state(nzp, ph);
-          V5<T> h1p = riemann<RS>(ztp, nzm, ph, &fails);  // H1(t+1/2)
+          tally.floors(floor_state(nzm, ph) + floor_state(nzp, ph));
+          int nf = 0;
+          V5<T> h1p = riemann<RS>(ztp, nzm, ph, &nf);  // H1(t+1/2)
+          tally.fails(nf);
           if (t >= 0) sts5(sDH, kSQ, sqc, from_frame<2>(sub5(h1p, h1m)));
           h1m = h1p;
         }
@@ -272,7 +285,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
                     fr);
         }
         ctu_trace<PPM>(wc, fl, fr, ph);
-        floors += floor_state(fl, ph) + floor_state(fr, ph);
+        tally.floors(floor_state(fl, ph) + floor_state(fr, ph));
         sts5(w, kSQ, r, fl);
         sts5(w + 5 * kSQ, kSQ, r, fr);
       }
@@ -286,7 +299,9 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
         const int i = r % 17 - 1, b = r / 17 - 1;  // face between cells i and i+1 of row b
         const T* w = sW + (d ? 10 * kSQ : 0);
         const int l = (b + 1) * 18 + (i + 1);
-        V5<T> F = riemann<RS>(lds5(w + 5 * kSQ, kSQ, l), lds5(w, kSQ, l + 1), ph, &fails);
+        int nf = 0;
+        V5<T> F = riemann<RS>(lds5(w + 5 * kSQ, kSQ, l), lds5(w, kSQ, l + 1), ph, &nf);
+        tally.fails(nf);
         sts5(sF1 + (d ? 5 * kF1 : 0), kF1, r, other_frame_d(F, d));
       }
       __syncthreads();
@@ -304,8 +319,11 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
         V5<T> d;
 #pragma unroll
         for (int n = 0; n < 5; ++n) d[n] = fz_[n] + gz_[n];
-        V5<T> cm = correct(ztm, d, ph, floors), cp = correct(ztp, d, ph, floors);
-        if (t >= 0) hn = from_frame<2>(riemann<RS>(zcp, cm, ph, &fails));  // H(t-1/2)
+        int nfl = 0, nf = 0;
+        V5<T> cm = correct(ztm, d, ph, nfl), cp = correct(ztp, d, ph, nfl);
+        if (t >= 0) hn = from_frame<2>(riemann<RS>(zcp, cm, ph, &nf));  // H(t-1/2)
+        tally.floors(nfl);
+        tally.fails(nf);
         zcp = cp;
       }
       if (t >= 0 && t <= 15) {
@@ -327,9 +345,12 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
 #pragma unroll
           for (int n = 0; n < 5; ++n) { dl[n] = ol[n] + Hl[n]; dr[n] = orr[n] + Hr[n]; }
           const int l = (b + 1) * 18 + (i + 1);
-          V5<T> L = correct(lds5(w + 5 * kSQ, kSQ, l), dl, ph, floors);
-          V5<T> R = correct(lds5(w, kSQ, l + 1), dr, ph, floors);
-          sts5(sF2 + (d ? 5 * kF2 : 0), kF2, r, riemann<RS>(L, R, ph, &fails));
+          int nfl = 0, nf = 0;
+          V5<T> L = correct(lds5(w + 5 * kSQ, kSQ, l), dl, ph, nfl);
+          V5<T> R = correct(lds5(w, kSQ, l + 1), dr, ph, nfl);
+          sts5(sF2 + (d ? 5 * kF2 : 0), kF2, r, riemann<RS>(L, R, ph, &nf));
+          tally.floors(nfl);
+          tally.fails(nf);
         }
       }
       __syncthreads();
@@ -375,7 +396,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
     }
     __syncthreads();
   }
-  flush_diag(a, fails, floors);
+  if (tid < 2 && a.diag && tally.c[tid]) atomicAdd(&a.diag[tid], (unsigned long long)tally.c[tid]);
 }
 
 }  // namespace ctu
