@@ -96,6 +96,25 @@ template <int G> HY_DEV Column<int> column_of(int tid) {
 }
 
 
+// Order in which a workgroup of the persistent grid visits the groups.
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup b runs on
+// XCD b % 8), each XCD with its own L2.  XCD x takes the x-th contiguous
+// eighth of the groups, so the workgroups resident on one XCD at a time work
+// on neighbouring groups (x, then y, then z neighbours are close in group
+// order) and the ghost cells they read from each other hit in that L2.  Any
+// grid that is not a multiple of 8 uses the plain strided order.
+struct GroupOrder {
+  long long first, stride, end;  // visits first, first + stride, ... < end
+};
+HY_DEV GroupOrder group_order(long long n_groups) {
+  const long long P = gridDim.x, b = blockIdx.x;
+  if (P < 8 || P % 8 != 0) return GroupOrder{b, P, n_groups};
+  const long long chunk = (n_groups + 7) / 8;
+  const long long lo = (b % 8) * chunk;
+  const long long hi = lo + chunk < n_groups ? lo + chunk : n_groups;
+  return GroupOrder{lo + b / 8, P / 8, hi};
+}
+
 // Per-launch physics constants (dt/dh set per group from its segment).
 template <typename T> HY_DEV Phys<T> make_phys(const FusedArgs<T>& a) {
   Phys<T> ph;

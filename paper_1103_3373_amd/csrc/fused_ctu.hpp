@@ -132,7 +132,8 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
   constexpr int nE = 19 * 18;
 
   int seg = 0;
-  for (long long grp = blockIdx.x; grp < a.n_groups; grp += gridDim.x) {
+  const GroupOrder order = group_order(a.n_groups);
+  for (long long grp = order.first; grp < order.end; grp += order.stride) {
     double dt;
     const Seg* S = find_seg(a, grp, seg, dt);
     const long long lg = grp - S->first;

@@ -42,7 +42,8 @@ __global__ void __launch_bounds__(kThreads, 2) vl_predict_kernel(FusedArgs<T> a)
   Phys<T> ph = make_phys(a);
 
   int seg = 0;
-  for (long long grp = blockIdx.x; grp < a.n_groups; grp += gridDim.x) {
+  const GroupOrder order = group_order(a.n_groups);
+  for (long long grp = order.first; grp < order.end; grp += order.stride) {
     double dt;
     const Seg* S = find_seg(a, grp, seg, dt);
     const long long lg = grp - S->first;

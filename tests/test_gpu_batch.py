@@ -181,8 +181,9 @@ def test_launch_shape_does_not_change_results(H):
 @pytest.mark.parametrize("recon,riemann", [(1, 1), (1, 0), (0, 2)])
 def test_every_launch_variant_gives_identical_results(H, recon, riemann):
     """CTU FP32 in each register-budget variant and several persistent
-    grid sizes (one group per workgroup, a ragged 7, the default) gives the
-    same bits on the box path and the ghosted-groups path."""
+    grid sizes (the default, a ragged 7, 16 = the XCD-blocked group order
+    with an empty last block, one group per workgroup) gives the same bits
+    on the box path and the ghosted-groups path."""
     gamma = 1.4
     n = 48
     box = random_smooth_box(n, gamma, 21 + recon + 2 * riemann, amp=0.3)
@@ -195,7 +196,7 @@ def test_every_launch_variant_gives_identical_results(H, recon, riemann):
     outs = []
     try:
         for variant in (4, 2):
-            for grid in (0, 7, B.shape[0]):
+            for grid in (0, 7, 16, B.shape[0]):
                 H.set_launch_shape(spec, grid, variant)
                 ob = torch.empty_like(B)
                 H.step_box(B, ob, (n, n, n), dt, **kw)
