@@ -13,62 +13,66 @@
 //   full dt.
 //
 // Per plane t (t = -1 .. 16): A columns (primitive plane t, z face states of
-// plane t) | B x/y slopes | C x/y face states | D (MHM) Hancock half step of
-// the cross cells by their column threads | E x/y Riemann faces of plane t
-// and the z Riemann face below it | F update of plane t-1 and boundary
-// fluxes.  Four (VL) or five (MHM) barriers per plane.
+// plane t) | B x/y slopes | (PPM) C1 x/y edges, once per face | C x/y face
+// states | D (MHM) Hancock half step of the cross cells by their column
+// threads | E x/y Riemann faces of plane t and the z Riemann face below it |
+// F update of plane t-1 and boundary fluxes.  As in the CTU kernel, every
+// per-direction LDS array is laid out in the direction's own (along,
+// across) coordinates and frame, with the primitive plane also kept
+// transposed in y-frame order, so x and y tasks share one code path.
 #pragma once
 
-#include "fused_common.hpp"
+#include "fused_ctu.hpp"
 
 namespace hy {
 namespace muscl {
 
 using namespace fz;
+using ctu::kP;
+using ctu::kS;
+using ctu::kSQ;
+using ctu::kF2;
+using ctu::Tally;
+using ctu::to_frame_d;
+using ctu::from_frame_d;
 
-constexpr int kNmax = 22;
-constexpr int kP = kNmax * kNmax;
-constexpr int kSX = 20 * 18;
-constexpr int kSY = 18 * 20;
-constexpr int kSQ = 18 * 18;
-constexpr int oP = 0;
-constexpr int oSX = oP + 5 * kP;
-constexpr int oSY = oSX + 5 * kSX;
-constexpr int oWX = oSY + 5 * kSY;
-constexpr int oWY = oWX + 10 * kSQ;
-constexpr int kLds = oWY + 10 * kSQ;
-constexpr int kF2 = 17 * 16;
-constexpr int kG2 = 16 * 17;
-constexpr int oF2 = oSX;
-constexpr int oG2 = oSX + 5 * kF2;
-static_assert(10 * kF2 <= 5 * (kSX + kSY), "F2/G2 alias");
+constexpr int oP = 0;               // [5][kP] lab order, (y+G) N + (x+G)
+constexpr int oQ = oP + 5 * kP;     // [5][kP] y frame, transposed: (x+G) N + (y+G)
+constexpr int oS = oQ + 5 * kP;     // [2][5][kS] frame of d, (b+1) 20 + (a+2)
+constexpr int oW = oS + 10 * kS;    // [2][2][5][kSQ] frame of d, (b+1) 18 + (a+1); side 0 = left face
+constexpr int kLds = oW + 20 * kSQ;
+constexpr int oF2 = oS;             // [2][5][kF2] frame of d, b 17 + (a+1): slopes are dead by then
+static_assert(10 * kF2 <= 10 * kS, "final fluxes alias the slopes");
+constexpr size_t kLdsBytes(size_t elem) { return kLds * elem + 2 * sizeof(unsigned); }
 
 template <typename T, bool PPM, int RS, int WAVES, int MODE>
 __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) {
+  constexpr int NT = kThreads;
   constexpr int G = PPM ? 3 : 2;
   constexpr int N = 16 + 2 * G;
   extern __shared__ unsigned char smem_raw[];
   T* sm = reinterpret_cast<T*>(smem_raw);
   T* sP = sm + oP;
-  T* sSX = sm + oSX;
-  T* sSY = sm + oSY;
-  T* sWX = sm + oWX;
-  T* sWY = sm + oWY;
+  T* sQ = sm + oQ;
+  T* sS = sm + oS;
+  T* sW = sm + oW;
   T* sF2 = sm + oF2;
-  T* sG2 = sm + oG2;
+  const Tally tally{reinterpret_cast<unsigned*>(smem_raw + kLds * sizeof(T))};
 
   const int tid = threadIdx.x;
   const Column<int> col = column_of<G>(tid);
   const int pcol = (col.y + G) * N + (col.x + G);
-  const int sqc = (col.y + 1) * 18 + (col.x + 1);
+  const int qcol = (col.x + G) * N + (col.y + G);
+  const int sqx = (col.y + 1) * 18 + (col.x + 1);  // the cross cell in the x arrays
+  const int sqy = (col.x + 1) * 18 + (col.y + 1);  // ... and in the (transposed) y arrays
   const bool interior = tid < 256;
-  int fails = 0, floors = 0;
+  if (tid < 2) tally.c[tid] = 0u;
+  __syncthreads();
   Phys<T> ph = make_phys(a);
 
-  constexpr int wSX = PPM ? 20 : 18, x0SX = PPM ? -2 : -1;
-  constexpr int nSX = wSX * 18;
-  constexpr int hSY = PPM ? 20 : 18, y0SY = PPM ? -2 : -1;
-  constexpr int nSY = 18 * hSY;
+  constexpr int wS = PPM ? 20 : 18, a0S = PPM ? -2 : -1;
+  constexpr int nS = wS * 18;
+  constexpr int nE = 19 * 18;
 
   int seg = 0;
   const GroupOrder order = group_order(a.n_groups);
@@ -100,6 +104,10 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
     };
     auto ucons = [&](int z) -> V5<T> { return MODE == 0 ? src.load(z) : upd.load(z); };
     auto zprim = [&](int z) -> V5<T> { return to_frame<2>(wprim(z)); };
+    auto put_plane = [&](int idx_p, int idx_q, const V5<T>& wl) {
+      sts5(sP, kP, idx_p, wl);
+      sts5(sQ, kP, idx_q, to_frame<1>(wl));
+    };
 
     // Column state (frame z):
     //   PPM: wa = W(t), wb = W(t+1), st = S(t), em = E(t-1/2)
@@ -107,7 +115,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
     V5<T> wa, wb, st, em;
     V5<T> zfm, zfp;   // z face states of plane t (half-stepped in MHM)
     V5<T> zhp;        // right z state of plane t-1
-    V5<T> hprev, accp;
+    V5<T> acc;        // flux differences of the plane being updated, all but its upper z face (lab)
     if (col.cross) {
       if (PPM) {
         V5<T> w3 = zprim(-3), w2 = zprim(-2);
@@ -123,10 +131,10 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
     }
 
     for (int t = -1; t <= 16; ++t) {
-      // ---- A: primitive plane t; z face states of plane t ------------------
+      // ---- A: primitive planes t; z face states of plane t -----------------
       if (col.cross) {
         if (PPM) {
-          sts5(sP, kP, pcol, from_frame<2>(wa));
+          put_plane(pcol, qcol, from_frame<2>(wa));
           V5<T> wc = zprim(t + 2);
           V5<T> sn = slope(wa, wb, wc, ph);
           V5<T> ep = ppm_edge(wa, wb, st, sn);
@@ -135,72 +143,81 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
           ppm_mono(wa, zfm, zfp);
           wa = wb; wb = wc; st = sn; em = ep;
         } else {
-          sts5(sP, kP, pcol, from_frame<2>(wb));
+          put_plane(pcol, qcol, from_frame<2>(wb));
           V5<T> wc = zprim(t + 1);
           V5<T> s0 = slope(wa, wb, wc, ph);
           plm_faces(wa, wb, wc, s0, ph, zfm, zfp);
           wa = wb; wb = wc;
         }
-        floors += floor_state(zfm, ph) + floor_state(zfp, ph);
+        tally.floors(floor_state(zfm, ph) + floor_state(zfp, ph));
       } else if (col.active) {
-        sts5(sP, kP, pcol, wprim(t));
+        put_plane(pcol, qcol, wprim(t));
       }
       __syncthreads();
 
       // ---- B: limited slopes along x and y ---------------------------------
-      for (int q = tid; q < nSX + nSY; q += kThreads) {
-        if (q < nSX) {
-          const int x = q % wSX + x0SX, y = q / wSX - 1;
-          const int c = (y + G) * N + (x + G);
-          V5<T> s = slope(to_frame<0>(lds5(sP, kP, c - 1)), to_frame<0>(lds5(sP, kP, c)),
-                          to_frame<0>(lds5(sP, kP, c + 1)), ph);
-          sts5(sSX, kSX, (y + 1) * 20 + (x + 2), s);
-        } else {
-          const int r = q - nSX;
-          const int x = r % 18 - 1, y = r / 18 + y0SY;
-          const int c = (y + G) * N + (x + G);
-          V5<T> s = slope(to_frame<1>(lds5(sP, kP, c - N)), to_frame<1>(lds5(sP, kP, c)),
-                          to_frame<1>(lds5(sP, kP, c + N)), ph);
-          sts5(sSY, kSY, (y + 2) * 18 + (x + 1), s);
-        }
+      for (int q = tid; q < 2 * nS; q += NT) {
+        const bool d = q >= nS;
+        const int r = d ? q - nS : q;
+        const int aa = r % wS + a0S, b = r / wS - 1;
+        const T* pl = d ? sQ : sP;
+        const int c = (b + G) * N + (aa + G);
+        V5<T> s = slope(lds5(pl, kP, c - 1), lds5(pl, kP, c), lds5(pl, kP, c + 1), ph);
+        sts5(sS + (d ? 5 * kS : 0), kS, (b + 1) * 20 + (aa + 2), s);
       }
       __syncthreads();
 
-      // ---- C: x and y face states (frame order) ----------------------------
-      for (int q = tid; q < 2 * kSQ; q += kThreads) {
-        const int r = q < kSQ ? q : q - kSQ;
-        const int x = r % 18 - 1, y = r / 18 - 1;
-        const int c = (y + G) * N + (x + G);
-        V5<T> fl, fr;
-        if (q < kSQ) {
-          V5<T> wm = to_frame<0>(lds5(sP, kP, c - 1)), w = to_frame<0>(lds5(sP, kP, c)),
-                wp = to_frame<0>(lds5(sP, kP, c + 1));
-          const int si = (y + 1) * 20 + (x + 2);
-          V5<T> s0 = lds5(sSX, kSX, si);
-          V5<T> smn = PPM ? lds5(sSX, kSX, si - 1) : s0, spl = PPM ? lds5(sSX, kSX, si + 1) : s0;
-          face_values<PPM>(wm, w, wp, smn, s0, spl, ph, fl, fr);
-          floors += floor_state(fl, ph) + floor_state(fr, ph);
-          sts5(sWX, kSQ, r, fl);
-          sts5(sWX + 5 * kSQ, kSQ, r, fr);
-        } else {
-          V5<T> wm = to_frame<1>(lds5(sP, kP, c - N)), w = to_frame<1>(lds5(sP, kP, c)),
-                wp = to_frame<1>(lds5(sP, kP, c + N));
-          const int si = (y + 2) * 18 + (x + 1);
-          V5<T> s0 = lds5(sSY, kSY, si);
-          V5<T> smn = PPM ? lds5(sSY, kSY, si - 18) : s0, spl = PPM ? lds5(sSY, kSY, si + 18) : s0;
-          face_values<PPM>(wm, w, wp, smn, s0, spl, ph, fl, fr);
-          floors += floor_state(fl, ph) + floor_state(fr, ph);
-          sts5(sWY, kSQ, r, fl);
-          sts5(sWY + 5 * kSQ, kSQ, r, fr);
+      // ---- C1 (PPM): x and y edge values, once per face --------------------
+      if (PPM) {
+        for (int q = tid; q < 2 * nE; q += NT) {
+          const bool d = q >= nE;
+          const int r = d ? q - nE : q;
+          const int aa = r % 19 - 2, b = r / 19 - 1;  // face between cells aa and aa+1
+          const T* pl = d ? sQ : sP;
+          const T* ss = sS + (d ? 5 * kS : 0);
+          const int c = (b + G) * N + (aa + G);
+          const int si = (b + 1) * 20 + (aa + 2);
+          V5<T> e = ppm_edge(lds5(pl, kP, c), lds5(pl, kP, c + 1), lds5(ss, kS, si), lds5(ss, kS, si + 1));
+          T* w = sW + (d ? 10 * kSQ : 0);
+          const int wi = (b + 1) * 18 + (aa + 1);
+          if (aa >= -1) sts5(w + 5 * kSQ, kSQ, wi, e);
+          if (aa <= 15) sts5(w, kSQ, wi + 1, e);
         }
+        __syncthreads();
+      }
+
+      // ---- C: x and y face states (frame of d) -----------------------------
+      for (int q = tid; q < 2 * kSQ; q += NT) {
+        const bool d = q >= kSQ;
+        const int r = d ? q - kSQ : q;
+        const int aa = r % 18 - 1, b = r / 18 - 1;
+        const T* pl = d ? sQ : sP;
+        const int c = (b + G) * N + (aa + G);
+        T* w = sW + (d ? 10 * kSQ : 0);
+        const V5<T> wc = lds5(pl, kP, c);
+        V5<T> fl, fr;
+        if (PPM) {
+          fl = lds5(w, kSQ, r);
+          fr = lds5(w + 5 * kSQ, kSQ, r);
+          ppm_mono(wc, fl, fr);
+        } else {
+          const T* ss = sS + (d ? 5 * kS : 0);
+          plm_faces(lds5(pl, kP, c - 1), wc, lds5(pl, kP, c + 1), lds5(ss, kS, (b + 1) * 20 + (aa + 2)), ph, fl,
+                    fr);
+        }
+        tally.floors(floor_state(fl, ph) + floor_state(fr, ph));
+        sts5(w, kSQ, r, fl);
+        sts5(w + 5 * kSQ, kSQ, r, fr);
       }
       __syncthreads();
 
       // ---- D (MHM): Hancock half step of every cross cell ------------------
       if (MODE == 0) {
         if (col.cross) {
-          V5<T> xm = lds5(sWX, kSQ, sqc), xp = lds5(sWX + 5 * kSQ, kSQ, sqc);
-          V5<T> ym = lds5(sWY, kSQ, sqc), yp = lds5(sWY + 5 * kSQ, kSQ, sqc);
+          T* wx = sW;
+          T* wy = sW + 10 * kSQ;
+          V5<T> xm = lds5(wx, kSQ, sqx), xp = lds5(wx + 5 * kSQ, kSQ, sqx);
+          V5<T> ym = lds5(wy, kSQ, sqy), yp = lds5(wy + 5 * kSQ, kSQ, sqy);
           V5<T> dU;
           {
             V5<T> fp = from_frame<0>(flux_of(xp, ph)), fm = from_frame<0>(flux_of(xm, ph));
@@ -218,12 +235,14 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
             for (int n = 0; n < 5; ++n) dU[n] += fp[n] - fm[n];
           }
           V5<T> dx = to_frame<0>(dU), dy = to_frame<1>(dU), dz = to_frame<2>(dU);
-          sts5(sWX, kSQ, sqc, correct(xm, dx, ph, floors));
-          sts5(sWX + 5 * kSQ, kSQ, sqc, correct(xp, dx, ph, floors));
-          sts5(sWY, kSQ, sqc, correct(ym, dy, ph, floors));
-          sts5(sWY + 5 * kSQ, kSQ, sqc, correct(yp, dy, ph, floors));
-          zfm = correct(zfm, dz, ph, floors);
-          zfp = correct(zfp, dz, ph, floors);
+          int nfl = 0;
+          sts5(wx, kSQ, sqx, correct(xm, dx, ph, nfl));
+          sts5(wx + 5 * kSQ, kSQ, sqx, correct(xp, dx, ph, nfl));
+          sts5(wy, kSQ, sqy, correct(ym, dy, ph, nfl));
+          sts5(wy + 5 * kSQ, kSQ, sqy, correct(yp, dy, ph, nfl));
+          zfm = correct(zfm, dz, ph, nfl);
+          zfp = correct(zfp, dz, ph, nfl);
+          tally.floors(nfl);
         }
         __syncthreads();
       }
@@ -231,23 +250,22 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
       // ---- E: Riemann solves: x/y faces of plane t, z face below it --------
       V5<T> hn;
       if (interior) {
-        if (t >= 0) hn = from_frame<2>(riemann<RS>(zhp, zfm, ph, &fails));  // H(t-1/2)
+        int nf = 0;
+        if (t >= 0) hn = from_frame<2>(riemann<RS>(zhp, zfm, ph, &nf));  // H(t-1/2)
+        tally.fails(nf);
         zhp = zfp;
       }
       if (t >= 0 && t <= 15) {
-        for (int q = kThreads - 1 - tid; q < kF2 + kG2; q += kThreads) {
-          if (q < kF2) {
-            const int i = q % 17 - 1, y = q / 17;
-            const int l = (y + 1) * 18 + (i + 1);
-            V5<T> F = riemann<RS>(lds5(sWX + 5 * kSQ, kSQ, l), lds5(sWX, kSQ, l + 1), ph, &fails);
-            sts5(sF2, kF2, q, from_frame<0>(F));
-          } else {
-            const int r = q - kF2;
-            const int x = r % 16, j = r / 16 - 1;
-            const int l = (j + 1) * 18 + (x + 1);
-            V5<T> F = riemann<RS>(lds5(sWY + 5 * kSQ, kSQ, l), lds5(sWY, kSQ, l + 18), ph, &fails);
-            sts5(sG2, kG2, r, from_frame<1>(F));
-          }
+        for (int q = NT - 1 - tid; q < 2 * kF2; q += NT) {
+          const bool d = q >= kF2;
+          const int r = d ? q - kF2 : q;
+          const int i = r % 17 - 1, b = r / 17;  // face between cells i and i+1 of row b
+          const T* w = sW + (d ? 10 * kSQ : 0);
+          const int l = (b + 1) * 18 + (i + 1);
+          int nf = 0;
+          V5<T> F = riemann<RS>(lds5(w + 5 * kSQ, kSQ, l), lds5(w, kSQ, l + 1), ph, &nf);
+          tally.fails(nf);
+          sts5(sF2 + (d ? 5 * kF2 : 0), kF2, r, F);
         }
       }
       __syncthreads();
@@ -259,14 +277,13 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
           V5<T> u = ucons(t - 1);
           const int o = ((t - 1) * 16 + y) * 16 + x;
 #pragma unroll
-          for (int n = 0; n < 5; ++n) O[n * 4096 + o] = u[n] - ph.dtdh * (accp[n] + (hn[n] - hprev[n]));
+          for (int n = 0; n < 5; ++n) O[n * 4096 + o] = u[n] - ph.dtdh * (acc[n] + hn[n]);
         }
-        if (t >= 0) hprev = hn;
         if (t >= 0 && t <= 15) {
           V5<T> fx = sub5(lds5(sF2, kF2, y * 17 + x + 1), lds5(sF2, kF2, y * 17 + x));
-          V5<T> gy = sub5(lds5(sG2, kG2, (y + 1) * 16 + x), lds5(sG2, kG2, y * 16 + x));
+          V5<T> gy = from_frame<1>(sub5(lds5(sF2 + 5 * kF2, kF2, x * 17 + y + 1), lds5(sF2 + 5 * kF2, kF2, x * 17 + y)));
 #pragma unroll
-          for (int n = 0; n < 5; ++n) accp[n] = fx[n] + gy[n];
+          for (int n = 0; n < 5; ++n) acc[n] = (fx[n] + gy[n]) - hn[n];  // hn is the lower z face of plane t
         }
         if (FO) {
           const int f = (t == 0) ? 0 : (t == 16 ? 1 : (t == 8 && a.nf == 3 ? 2 : -1));
@@ -278,17 +295,18 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
       } else if (FO && t >= 0 && t <= 15) {
         const int q = tid - 256;
         if (q < 2 * a.nf * 16) {
-          const int d = q / (a.nf * 16), f = (q / 16) % a.nf, s = q % 16;
+          const bool d = q >= a.nf * 16;
+          const int f = (q / 16) % a.nf, s = q % 16;
           const int fi = f == 0 ? -1 : (f == 1 ? 15 : 7);
-          V5<T> v = d == 0 ? lds5(sF2, kF2, s * 17 + fi + 1) : lds5(sG2, kG2, (fi + 1) * 16 + s);
+          const V5<T> v = from_frame_d(lds5(sF2 + (d ? 5 * kF2 : 0), kF2, s * 17 + fi + 1), d);
 #pragma unroll
-          for (int n = 0; n < 5; ++n) FO[((d * a.nf + f) * 5 + n) * 256 + t * 16 + s] = v[n];
+          for (int n = 0; n < 5; ++n) FO[(((d ? 1 : 0) * a.nf + f) * 5 + n) * 256 + t * 16 + s] = v[n];
         }
       }
     }
     __syncthreads();
   }
-  flush_diag(a, fails, floors);
+  if (tid < 2 && a.diag && tally.c[tid]) atomicAdd(&a.diag[tid], (unsigned long long)tally.c[tid]);
 }
 
 }  // namespace muscl

@@ -8,7 +8,7 @@ namespace hy {
 template <int MODE, bool PPM, int RS, int WAVES>
 static hipError_t launch_one(const FusedArgs<float>& a, int grid, hipStream_t st) {
   auto k = muscl::muscl_kernel<float, PPM, RS, WAVES, MODE>;
-  const size_t shm = (size_t)muscl::kLds * sizeof(float);
+  const size_t shm = muscl::kLdsBytes(sizeof(float));
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
