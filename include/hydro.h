@@ -207,7 +207,7 @@ int hydro_autotune(const struct hydro_spec* spec, int n_groups_hint, void* strea
  * Pins the launch shape of the fused kernel for `spec`'s specialization in
  * the in-process cache (as if the autotuner had chosen it), for callers that
  * tune offline or need a fixed shape.  grid = persistent workgroup count
- * (0 = default: one or six workgroups per compute unit, by variant; a grid
+ * (0 = default: one or twelve workgroups per compute unit, by variant; a grid
  * larger than a launch's group count is clamped to it).  variant = register
  * budget variant: 2 (one workgroup per CU, no register spills) or 4 (two
  * workgroups per CU; FP32 only).  Results do not depend on the shape.

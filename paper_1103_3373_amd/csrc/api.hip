@@ -202,12 +202,13 @@ int cu_count() {
 Tune tuned(int f64, int scheme, int recon, int riemann, int charlim, long long n_groups) {
   tune_load();
   auto it = g_tune.find(tune_key(f64, scheme, recon, riemann, charlim));
-  // Untuned default: the two-workgroups-per-CU register variant with six
-  // workgroups per CU in flight over the persistent loop (the autotuner's
-  // choice for CTU on MI355X); FP64 has one variant only.
+  // Untuned default: the two-workgroups-per-CU register variant with twelve
+  // workgroups per CU over the persistent loop (about the autotuner's choice
+  // for CTU on MI355X: more, shorter workgroups even out the tail); FP64 has
+  // one variant only.
   Tune t = (it != g_tune.end()) ? it->second : Tune{0, 4};
   if (f64) t.waves = 2;
-  if (t.grid <= 0) t.grid = cu_count() * (t.waves == 4 ? 6 : 1);
+  if (t.grid <= 0) t.grid = cu_count() * (t.waves == 4 ? 12 : 1);
   if (t.grid > n_groups) t.grid = (int)n_groups;
   if (t.grid < 1) t.grid = 1;
   return t;
@@ -588,7 +589,7 @@ int hydro_autotune(const struct hydro_spec* spec, int n_groups_hint, void* strea
     vl = w.vl;
   }
   // Candidates: register variant x persistent grid (multiples of the CU count).
-  const int mults[] = {1, 2, 3, 4, 6, 8};
+  const int mults[] = {1, 2, 3, 4, 6, 8, 12, 16};
   const int variants[] = {2, 4};
   Tune best{-1, 2};
   float best_ms = 1e30f;
