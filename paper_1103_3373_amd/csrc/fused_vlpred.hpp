@@ -53,7 +53,7 @@ __global__ void __launch_bounds__(kThreads, 2) vl_predict_kernel(FusedArgs<T> a)
     rd.init(S, lg, active ? x : 0, active ? y : 0);
     T* __restrict__ Wo = a.wstar + grp * 5 * NCs + ((long)(y + Gs) * Ns + (x + Gs));
 
-    V5<T> u0, w0, u1, w1, hm;
+    V5<T> u0, w0, u1, w1, hm, unext;
     if (active) {
       u0 = rd.load(-Gs - 1);
       w0 = prim_of(u0, ph);
@@ -62,13 +62,17 @@ __global__ void __launch_bounds__(kThreads, 2) vl_predict_kernel(FusedArgs<T> a)
       if (out_col) hm = from_frame<2>(riemann<RS>(to_frame<2>(w0), to_frame<2>(w1), ph, &fails));
       u0 = u1;
       w0 = w1;
+      unext = rd.load(-Gs + 1);
     }
     for (int z = -Gs; z <= 15 + Gs; ++z) {
-      // ---- A: plane z to LDS; z flux above the column's cell ----------------
+      // ---- A: plane z to LDS; z flux above the column's cell.  The column's
+      //         plane z+1 was loaded one plane ahead; plane z+2 is requested
+      //         now and arrives while phases B and C run --------------------
       V5<T> hp;
       if (active) {
         sts5(sP, N * N, tid, w0);
-        u1 = rd.load(z + 1);
+        u1 = unext;
+        if (z + 2 <= 16 + Gs) unext = rd.load(z + 2);
         w1 = prim_of(u1, ph);
         if (out_col) hp = from_frame<2>(riemann<RS>(to_frame<2>(w0), to_frame<2>(w1), ph, &fails));
       }
