@@ -116,6 +116,8 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
     V5<T> zfm, zfp;   // z face states of plane t (half-stepped in MHM)
     V5<T> zhp;        // right z state of plane t-1
     V5<T> acc;        // flux differences of the plane being updated, all but its upper z face (lab)
+    V5<T> wnext;      // the column's newest z plane, loaded one plane ahead (prims)
+    constexpr int zAhead = PPM ? 2 : 1;
     if (col.cross) {
       if (PPM) {
         V5<T> w3 = zprim(-3), w2 = zprim(-2);
@@ -128,6 +130,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
         wa = zprim(-2);
         wb = zprim(-1);
       }
+      wnext = src.load(-1 + zAhead);
     }
 
     for (int t = -1; t <= 16; ++t) {
@@ -135,7 +138,8 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
       if (col.cross) {
         if (PPM) {
           put_plane(pcol, qcol, from_frame<2>(wa));
-          V5<T> wc = zprim(t + 2);
+          V5<T> wc = to_frame<2>(MODE == 0 ? prim_of(wnext, ph) : wnext);  // plane t + 2
+          if (t + 1 + zAhead <= 16 + zAhead) wnext = src.load(t + 1 + zAhead);
           V5<T> sn = slope(wa, wb, wc, ph);
           V5<T> ep = ppm_edge(wa, wb, st, sn);
           zfm = em;
@@ -144,7 +148,8 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
           wa = wb; wb = wc; st = sn; em = ep;
         } else {
           put_plane(pcol, qcol, from_frame<2>(wb));
-          V5<T> wc = zprim(t + 1);
+          V5<T> wc = to_frame<2>(MODE == 0 ? prim_of(wnext, ph) : wnext);  // plane t + 1
+          if (t + 1 + zAhead <= 16 + zAhead) wnext = src.load(t + 1 + zAhead);
           V5<T> s0 = slope(wa, wb, wc, ph);
           plm_faces(wa, wb, wc, s0, ph, zfm, zfp);
           wa = wb; wb = wc;
