@@ -249,3 +249,56 @@ def test_cfl_dt_batch_equals_single(H):
         torch.cuda.synchronize()
         assert dt.item() == single.item()
         assert dt.item() == O.cfl_dt(st.cpu().numpy().astype(np.float64), 1.0 / n, gamma, 0.4)
+
+
+def _two_state_box(n, left, right, gamma):
+    """Box split at x = 1/2 into two uniform primitive states (rho, u, p)."""
+    x = (np.arange(n) + 0.5) / n
+    sel = (x < 0.5)[None, None, :] * np.ones((n, n, 1), dtype=bool)
+    rho = np.where(sel, left[0], right[0])
+    u = np.where(sel, left[1], right[1])
+    p = np.where(sel, left[2], right[2])
+    return W.primitive_to_conserved(rho, u, 0 * u, 0 * u, p, gamma)
+
+
+@pytest.mark.parametrize("case", ["roe_fallback", "floors"])
+def test_diagnostic_counts_do_not_depend_on_launch_shape(H, case):
+    """Roe fallbacks (strong double rarefaction) and floor hits (a region
+    below the pressure floor) are counted on the device; the totals are the
+    same for every launch shape and for the box and ghosted-groups paths,
+    in FP32 and FP64."""
+    gamma, n = 1.4, 32
+    if case == "roe_fallback":
+        box = _two_state_box(n, (1.0, -2.0, 0.4), (1.0, 2.0, 0.4), gamma)
+        riemann, key = H.ROE, "roe_fallbacks"
+    else:
+        box = _two_state_box(n, (1.0, 0.0, 1.0), (1e-9, 3.0, 1e-11), gamma)
+        riemann, key = H.HLLC, "floor_hits"
+    g = H.ghost_width(H.CTU, H.PPM)
+    for dtype in (torch.float32, torch.float64):
+        B = _dev(W.box_to_groups(box), dtype)
+        G = H.fill_ghosts_periodic(_dev(box, dtype), g)
+        f64 = dtype == torch.float64
+        spec = H.make_spec(H.CTU, H.PPM, riemann, gamma=gamma, char=True, f64=f64)
+        dt = torch.full((1,), 1e-3, dtype=torch.float64, device="cuda")
+        kw = dict(dh=1 / n, gamma=gamma, scheme=H.CTU, recon=H.PPM, riemann=riemann, char=True)
+        counts = {}
+        try:
+            for variant, grid in ((2, 0), (2, 7), (2, 16)) + (() if f64 else ((4, 0), (4, B.shape[0]))):
+                H.set_launch_shape(spec, grid, variant)
+                H.get_diag(reset=True)
+                ob = torch.empty_like(B)
+                H.step_box(B, ob, (n, n, n), dt, **kw)
+                db = H.get_diag(reset=True)
+                og = torch.empty_like(B)
+                H.solve_groups(G, og, None, dt=1e-3, **kw)
+                dg = H.get_diag(reset=True)
+                assert torch.isfinite(ob).all() and torch.equal(ob, og)
+                counts[(variant, grid, "box")] = db
+                counts[(variant, grid, "groups")] = dg
+        finally:
+            H.set_launch_shape(spec, 0, 2 if f64 else 4)
+        first = next(iter(counts.values()))
+        assert first[key] > 0, (dtype, first)
+        for shape, d in counts.items():
+            assert d == first, (dtype, shape, d, first)
