@@ -32,6 +32,15 @@
  *    gives the message of the last failure on the calling thread.
  *  - Numerical trouble is never an error: Roe fallbacks and floor
  *    activations are counted on the device (hydro_get_diag).
+ *  - Library-owned device memory: the diagnostics counters and a pool of
+ *    reduction partials are allocated at the first call on a device; the
+ *    plain path's temporaries, the VL half-step scratch and the per-group
+ *    partials of hydro_cfl_dt_batch are allocated per (device, stream) the
+ *    first time a call needs them at a given size (growing synchronizes the
+ *    device).  A call that would allocate must not be the first of its kind
+ *    inside a graph capture; hydro_cfl_dt and hydro_conserved_sums never
+ *    allocate after the first call on the device (up to 64 streams).
+ *    hydro_shutdown frees all of it.
  */
 #ifndef HYDRO_H
 #define HYDRO_H
