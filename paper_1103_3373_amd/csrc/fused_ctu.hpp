@@ -95,7 +95,12 @@ template <typename T> HY_DEV V5<T> other_frame_d(const V5<T>& v, bool d) {
 // WAVES = minimum waves per SIMD the register allocation must allow: 2 gives
 // one workgroup per CU without spills, 4 gives two workgroups per CU (with
 // some spilling); the autotuner picks per specialization.
-template <typename T, bool PPM, int RS, int WAVES>
+//
+// FAST: the configuration of every production workload (van Leer limiter on
+// characteristic variables) is compiled with those two choices fixed, so the
+// limiter takes no run-time branch per component (about 10% of the kernel);
+// every other combination runs the same code with run-time choices.
+template <typename T, bool PPM, int RS, int WAVES, bool FAST>
 __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T> a) {
   constexpr int NT = kThreads;
   constexpr int G = PPM ? 3 : 2;
@@ -124,6 +129,10 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
   __syncthreads();
 
   Phys<T> ph = make_phys(a);
+  if (FAST) {
+    ph.limiter = 1;  // van Leer
+    ph.charlim = 1;
+  }
 
   // Task counts per direction.  Slopes: PPM needs a in -2..17 (edges of the
   // traced cells), PLM a in -1..16.  PPM edges: faces a+1/2, a in -2..16.

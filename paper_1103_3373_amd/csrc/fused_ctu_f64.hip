@@ -3,9 +3,9 @@
 
 namespace hy {
 
-template <bool PPM, int RS, int WAVES>
+template <bool PPM, int RS, int WAVES, bool FAST>
 static hipError_t launch_one(const FusedArgs<double>& a, int grid, hipStream_t st) {
-  auto k = ctu::ctu_fused_kernel<double, PPM, RS, WAVES>;
+  auto k = ctu::ctu_fused_kernel<double, PPM, RS, WAVES, FAST>;
   const size_t shm = ctu::kLdsBytes(sizeof(double));
   static bool attr = false;
   if (!attr) {
@@ -17,16 +17,22 @@ static hipError_t launch_one(const FusedArgs<double>& a, int grid, hipStream_t s
   return hipGetLastError();
 }
 
+template <int WAVES, bool FAST>
+static hipError_t launch_wf(const FusedArgs<double>& a, int recon, int riemann, int grid, hipStream_t st) {
+  if (recon == 1) {
+    if (riemann == 0) return launch_one<true, 0, WAVES, FAST>(a, grid, st);
+    if (riemann == 1) return launch_one<true, 1, WAVES, FAST>(a, grid, st);
+    return launch_one<true, 2, WAVES, FAST>(a, grid, st);
+  }
+  if (riemann == 0) return launch_one<false, 0, WAVES, FAST>(a, grid, st);
+  if (riemann == 1) return launch_one<false, 1, WAVES, FAST>(a, grid, st);
+  return launch_one<false, 2, WAVES, FAST>(a, grid, st);
+}
+
 template <int WAVES>
 static hipError_t launch_w(const FusedArgs<double>& a, int recon, int riemann, int grid, hipStream_t st) {
-  if (recon == 1) {
-    if (riemann == 0) return launch_one<true, 0, WAVES>(a, grid, st);
-    if (riemann == 1) return launch_one<true, 1, WAVES>(a, grid, st);
-    return launch_one<true, 2, WAVES>(a, grid, st);
-  }
-  if (riemann == 0) return launch_one<false, 0, WAVES>(a, grid, st);
-  if (riemann == 1) return launch_one<false, 1, WAVES>(a, grid, st);
-  return launch_one<false, 2, WAVES>(a, grid, st);
+  if (a.limiter == 1 && a.charlim == 1) return launch_wf<WAVES, true>(a, recon, riemann, grid, st);
+  return launch_wf<WAVES, false>(a, recon, riemann, grid, st);
 }
 
 hipError_t launch_ctu_f64(const FusedArgs<double>& a, int recon, int riemann, const FusedCfg& cfg, hipStream_t st) {

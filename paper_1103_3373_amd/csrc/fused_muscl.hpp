@@ -45,7 +45,9 @@ constexpr int oF2 = oS;             // [2][5][kF2] frame of d, b 17 + (a+1): slo
 static_assert(10 * kF2 <= 10 * kS, "final fluxes alias the slopes");
 constexpr size_t kLdsBytes(size_t elem) { return kLds * elem + 2 * sizeof(unsigned); }
 
-template <typename T, bool PPM, int RS, int WAVES, int MODE>
+// FAST as in the CTU kernel: van Leer on characteristic variables fixed at
+// compile time.
+template <typename T, bool PPM, int RS, int WAVES, int MODE, bool FAST>
 __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) {
   constexpr int NT = kThreads;
   constexpr int G = PPM ? 3 : 2;
@@ -69,6 +71,10 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
   if (tid < 2) tally.c[tid] = 0u;
   __syncthreads();
   Phys<T> ph = make_phys(a);
+  if (FAST) {
+    ph.limiter = 1;  // van Leer
+    ph.charlim = 1;
+  }
 
   constexpr int wS = PPM ? 20 : 18, a0S = PPM ? -2 : -1;
   constexpr int nS = wS * 18;

@@ -5,9 +5,9 @@
 
 namespace hy {
 
-template <int MODE, bool PPM, int RS, int WAVES>
+template <int MODE, bool PPM, int RS, int WAVES, bool FAST>
 static hipError_t launch_one(const FusedArgs<double>& a, int grid, hipStream_t st) {
-  auto k = muscl::muscl_kernel<double, PPM, RS, WAVES, MODE>;
+  auto k = muscl::muscl_kernel<double, PPM, RS, WAVES, MODE, FAST>;
   const size_t shm = muscl::kLdsBytes(sizeof(double));
   static bool attr = false;
   if (!attr) {
@@ -19,16 +19,22 @@ static hipError_t launch_one(const FusedArgs<double>& a, int grid, hipStream_t s
   return hipGetLastError();
 }
 
+template <int MODE, int WAVES, bool FAST>
+static hipError_t launch_wf(const FusedArgs<double>& a, int recon, int riemann, int grid, hipStream_t st) {
+  if (recon == 1) {
+    if (riemann == 0) return launch_one<MODE, true, 0, WAVES, FAST>(a, grid, st);
+    if (riemann == 1) return launch_one<MODE, true, 1, WAVES, FAST>(a, grid, st);
+    return launch_one<MODE, true, 2, WAVES, FAST>(a, grid, st);
+  }
+  if (riemann == 0) return launch_one<MODE, false, 0, WAVES, FAST>(a, grid, st);
+  if (riemann == 1) return launch_one<MODE, false, 1, WAVES, FAST>(a, grid, st);
+  return launch_one<MODE, false, 2, WAVES, FAST>(a, grid, st);
+}
+
 template <int MODE, int WAVES>
 static hipError_t launch_w(const FusedArgs<double>& a, int recon, int riemann, int grid, hipStream_t st) {
-  if (recon == 1) {
-    if (riemann == 0) return launch_one<MODE, true, 0, WAVES>(a, grid, st);
-    if (riemann == 1) return launch_one<MODE, true, 1, WAVES>(a, grid, st);
-    return launch_one<MODE, true, 2, WAVES>(a, grid, st);
-  }
-  if (riemann == 0) return launch_one<MODE, false, 0, WAVES>(a, grid, st);
-  if (riemann == 1) return launch_one<MODE, false, 1, WAVES>(a, grid, st);
-  return launch_one<MODE, false, 2, WAVES>(a, grid, st);
+  if (a.limiter == 1 && a.charlim == 1) return launch_wf<MODE, WAVES, true>(a, recon, riemann, grid, st);
+  return launch_wf<MODE, WAVES, false>(a, recon, riemann, grid, st);
 }
 
 hipError_t launch_muscl_f64(const FusedArgs<double>& a, int mode, int recon, int riemann, const FusedCfg& cfg,
