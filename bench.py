@@ -467,8 +467,7 @@ def main():
         if record:
             e1.record(stream)
             k_ev.append((e0, e1))
-        H.cfl_dt(dst, dh, gamma, cfl, dt_out=dt_dev)       # a9
-        H.conserved_sums(dst, dh, sums_out=sums)           # a10
+        H.cfl_dt_sums(dst, dh, gamma, cfl, dt_out=dt_dev, sums_out=sums)  # a9 + a10, one pass
 
     print(f"[bench] warmup {args.warmup} steps", file=sys.stderr, flush=True)
     for i in range(args.warmup):
@@ -566,7 +565,7 @@ def main():
         "data": "synthetic (seeded lognormal density, Mach-1 smooth velocities, 4 blasts p=100 r=8)",
         "config": {"workload": f"{n}^3 periodic box, {G} patch groups of 16^3 + 3 ghost cells, CTU+PPM(char, van "
                                f"Leer)+HLLC, gamma 1.4, CFL 0.5", "n_groups": G, "ghost": g,
-                   "step": "fused box solve (ghosts read from the resident box) + FP64 dt + FP64 sums"},
+                   "step": "fused box solve (ghosts read from the resident box) + FP64 dt and sums (one pass)"},
         "p50_step_ms": float(np.percentile(per_step, 50)),
         "graph_ms_per_step": graph_ms,
         "p99_step_ms": float(np.percentile(per_step, 99)),

@@ -119,6 +119,16 @@ int hydro_cfl_dt(const void* U, int n_groups, double dh, double gamma, double cf
 int hydro_conserved_sums(const void* U, int n_groups, double dh, int flags, double* sums_out, void* stream);
 
 /*
+ * Both of the above (Sec. 4.3 time step and the FP64 conserved sums) in one
+ * pass over U[n_groups][5][4096]: dt_out (device, 1 double) and sums_out
+ * (device, 5 doubles) are bit-identical to hydro_cfl_dt and
+ * hydro_conserved_sums on the same data, and the state is read once.
+ * dt_out and sums_out must not overlap (HYDRO_EALIAS).
+ */
+int hydro_cfl_dt_sums(const void* U, int n_groups, double dh, double gamma, double cfl, int flags, double* dt_out,
+                      double* sums_out, void* stream);
+
+/*
  * Preparation step (Sec. 4.2), periodic box: build the ghosted groups
  * [G][5][N][N][N] (N = 16 + 2g, G = (gz*ngy + gy)*ngx + gx) from a box
  * [5][nz][ny][nx] (or [G][5][16][16][16] with HYDRO_BOX_GROUPED).  nx, ny,

@@ -56,7 +56,7 @@ struct Workspace {
   long long seg_partial_n = 0;
   void* vl = nullptr;  // VL half-step scratch (fused path)
   size_t vl_bytes = 0;
-  double* partial = nullptr;  // reduction partials (a pool slot or own memory)
+  double* partial = nullptr;  // reduction partials, kPartials x 6 doubles (a pool slot or own memory)
   bool own_partial = false;
 };
 const int kPartialSlots = 64;
@@ -88,7 +88,7 @@ int device_state(DeviceState** out) {
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(diag)");
     e = hipMemset(d.diag, 0, 2 * sizeof(unsigned long long));
     if (e != hipSuccess) return hip_fail(e, "hipMemset(diag)");
-    e = hipMalloc((void**)&d.partial_pool, (size_t)kPartialSlots * kPartials * 5 * sizeof(double));
+    e = hipMalloc((void**)&d.partial_pool, (size_t)kPartialSlots * kPartials * 6 * sizeof(double));
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(partial pool)");
   }
   *out = &d;
@@ -127,10 +127,10 @@ int ensure_vl(Workspace& w, size_t bytes) {
 int ensure_partial(DeviceState& d, Workspace& w) {
   if (w.partial) return 0;
   if (d.partial_used < kPartialSlots) {
-    w.partial = d.partial_pool + (size_t)(d.partial_used++) * kPartials * 5;
+    w.partial = d.partial_pool + (size_t)(d.partial_used++) * kPartials * 6;
     return 0;
   }
-  hipError_t e = hipMalloc((void**)&w.partial, (size_t)kPartials * 5 * sizeof(double));
+  hipError_t e = hipMalloc((void**)&w.partial, (size_t)kPartials * 6 * sizeof(double));
   if (e != hipSuccess) return hip_fail(e, "hipMalloc(partials)");
   w.own_partial = true;
   return 0;
@@ -402,6 +402,29 @@ int hydro_cfl_dt(const void* U, int n_groups, double dh, double gamma, double cf
   if (e != hipSuccess) return hip_fail(e, "max speed");
   e = hy::launch_dt_finish(w.partial, kPartials, dh, cfl, dt_out, st);
   if (e != hipSuccess) return hip_fail(e, "dt finish");
+  return 0;
+}
+
+int hydro_cfl_dt_sums(const void* U, int n_groups, double dh, double gamma, double cfl, int flags, double* dt_out,
+                      double* sums_out, void* stream) {
+  g_err[0] = 0;
+  if (n_groups <= 0) return fail(HYDRO_EINVAL, "n_groups must be positive");
+  if (!U || !dt_out || !sums_out) return fail(HYDRO_EINVAL, "null pointer");
+  if (!(dh > 0.0) || !(gamma > 1.0) || !(cfl > 0.0)) return fail(HYDRO_EINVAL, "dh, cfl > 0 and gamma > 1 required");
+  if (flags & ~kKnownFlags) return fail(HYDRO_EINVAL, "unknown flag bits");
+  if (overlap(dt_out, sizeof(double), sums_out, 5 * sizeof(double))) return fail(HYDRO_EALIAS, "dt_out overlaps sums_out");
+  hipStream_t st = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lock(g_mu);
+  DeviceState* ds;
+  if (int rc = device_state(&ds)) return rc;
+  Workspace& w = ds->ws[st];
+  if (int rc = ensure_partial(*ds, w)) return rc;
+  hipError_t e = (flags & HYDRO_F64)
+                     ? hy::launch_dtsums((const double*)U, n_groups, dh, gamma, cfl, w.partial, kPartials, dt_out,
+                                         sums_out, st)
+                     : hy::launch_dtsums((const float*)U, n_groups, dh, gamma, cfl, w.partial, kPartials, dt_out,
+                                         sums_out, st);
+  if (e != hipSuccess) return hip_fail(e, "dt and sums");
   return 0;
 }
 

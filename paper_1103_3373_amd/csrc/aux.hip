@@ -337,4 +337,98 @@ template hipError_t launch_sums<float>(const float*, long long, long long, doubl
 template hipError_t launch_sums<double>(const double*, long long, long long, double, double*, int, double*,
                                         hipStream_t);
 
+// ---------------------------------------------------------------------------
+// Time step and conserved sums in one pass over the state.  Workgroup w takes
+// the same contiguous slice, lane order and shuffle trees as sums_kernel, and
+// evaluates the signal speed with the same expression as maxspeed_kernel on
+// the same cells; the finish repeats dt_finish_kernel and sums_finish_kernel.
+// Both results are therefore bit-identical to the two separate reductions,
+// while the state is read once.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) dtsums_kernel(const T* __restrict__ U, long long n_blocks, double gamma,
+                                                     double* __restrict__ partial) {
+#pragma clang fp contract(off)
+  __shared__ double red[6][4];
+  const long long total = n_blocks << 12;
+  const long long per = (total + gridDim.x - 1) / gridDim.x;
+  const long long lo = blockIdx.x * per, hi = min(total, lo + per);
+  double s[5] = {0, 0, 0, 0, 0};
+  double m = 0.0;
+  for (long long t = lo + threadIdx.x; t < hi; t += blockDim.x) {
+    const T* u = U + ((t >> 12) * 5 << 12) + (t & 4095);
+    double c[5];
+#pragma unroll
+    for (int n = 0; n < 5; ++n) c[n] = (double)u[n * 4096];
+#pragma unroll
+    for (int n = 0; n < 5; ++n) s[n] += c[n];
+    const double rho = c[0];
+    const double mx = c[1], my = c[2], mz = c[3];
+    const double vx = mx / rho, vy = my / rho, vz = mz / rho;
+    const double ke = 0.5 * (mx * vx + my * vy + mz * vz);
+    const double p = (gamma - 1.0) * (c[4] - ke);
+    const double cs = __builtin_sqrt(gamma * p / rho);
+    double av = __builtin_fabs(vx);
+    if (__builtin_fabs(vy) > av) av = __builtin_fabs(vy);
+    if (__builtin_fabs(vz) > av) av = __builtin_fabs(vz);
+    const double sp = av + cs;
+    m = sp > m ? sp : m;
+  }
+#pragma unroll
+  for (int n = 0; n < 5; ++n) {
+    double v = wave_sum(s[n]);
+    if ((threadIdx.x & 63) == 0) red[n][threadIdx.x >> 6] = v;
+  }
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) red[5][threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x < 5) {
+    const int n = threadIdx.x;
+    partial[(long long)blockIdx.x * 5 + n] = (red[n][0] + red[n][1]) + (red[n][2] + red[n][3]);
+  } else if (threadIdx.x == 5) {
+    partial[(long long)gridDim.x * 5 + blockIdx.x] = fmax(fmax(red[5][0], red[5][1]), fmax(red[5][2], red[5][3]));
+  }
+}
+
+__global__ void __launch_bounds__(256) dtsums_finish_kernel(const double* __restrict__ partial, int n, double dh,
+                                                           double cfl, double* __restrict__ dt_out,
+                                                           double* __restrict__ sums_out) {
+#pragma clang fp contract(off)
+  __shared__ double red[6][4];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < n; b += blockDim.x) s += partial[(long long)b * 5 + v];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[v][threadIdx.x >> 6] = s;
+  }
+  double m = 0.0;
+  for (int t = threadIdx.x; t < n; t += blockDim.x) m = fmax(m, partial[(long long)n * 5 + t]);
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) red[5][threadIdx.x >> 6] = m;
+  __syncthreads();
+  const double vol = dh * dh * dh;
+  if (threadIdx.x < 5) {
+    const int v = threadIdx.x;
+    sums_out[v] = ((red[v][0] + red[v][1]) + (red[v][2] + red[v][3])) * vol;
+  } else if (threadIdx.x == 5) {
+    const double mx = fmax(fmax(red[5][0], red[5][1]), fmax(red[5][2], red[5][3]));
+    dt_out[0] = cfl * dh / mx;
+  }
+}
+
+template <typename T>
+hipError_t launch_dtsums(const T* U, long long n_blocks, double dh, double gamma, double cfl, double* partial,
+                         int n_partial, double* dt_out, double* sums_out, hipStream_t st) {
+  dtsums_kernel<T><<<dim3(n_partial), dim3(256), 0, st>>>(U, n_blocks, gamma, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  dtsums_finish_kernel<<<dim3(1), dim3(256), 0, st>>>(partial, n_partial, dh, cfl, dt_out, sums_out);
+  return hipGetLastError();
+}
+template hipError_t launch_dtsums<float>(const float*, long long, double, double, double, double*, int, double*,
+                                         double*, hipStream_t);
+template hipError_t launch_dtsums<double>(const double*, long long, double, double, double, double*, int, double*,
+                                          double*, hipStream_t);
+
 }  // namespace hy

@@ -88,5 +88,8 @@ hipError_t launch_dt_finish(const double* partial, int n_partial, double dh, dou
 template <typename T>
 hipError_t launch_sums(const T* U, long long n_blocks, long long cells, double dh, double* partial, int n_partial,
                        double* sums_out, hipStream_t st);
+template <typename T>
+hipError_t launch_dtsums(const T* U, long long n_blocks, double dh, double gamma, double cfl, double* partial,
+                         int n_partial, double* dt_out, double* sums_out, hipStream_t st);
 
 }  // namespace hy

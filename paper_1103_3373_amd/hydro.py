@@ -22,7 +22,7 @@ GMINMOD, VANLEER, VANALBADA, HYBRID = 0, 1, 2, 3
 F64, CHAR, FLUX_MID, PLAIN, ROE_FB_HLLC, BOX_GROUPED = 0x01, 0x02, 0x04, 0x08, 0x10, 0x20
 
 EXPORTS = (
-    "hydro_ghost_width", "hydro_solve_groups", "hydro_cfl_dt", "hydro_conserved_sums",
+    "hydro_ghost_width", "hydro_solve_groups", "hydro_cfl_dt", "hydro_conserved_sums", "hydro_cfl_dt_sums",
     "hydro_fill_ghosts_periodic", "hydro_fill_groups_interp", "hydro_solve_batch", "hydro_autotune",
     "hydro_set_launch_shape", "hydro_step_box", "hydro_cfl_dt_batch",
     "hydro_get_diag", "hydro_last_error", "hydro_shutdown",
@@ -70,6 +70,8 @@ def lib() -> ctypes.CDLL:
     L.hydro_cfl_dt.argtypes = [P, i, d, d, d, i, P, P]
     L.hydro_cfl_dt.restype = i
     L.hydro_conserved_sums.argtypes = [P, i, d, i, P, P]
+    L.hydro_cfl_dt_sums.argtypes = [P, i, d, d, d, i, P, P, P]
+    L.hydro_cfl_dt_sums.restype = i
     L.hydro_conserved_sums.restype = i
     L.hydro_fill_ghosts_periodic.argtypes = [P, i, i, i, i, i, P, P]
     L.hydro_fill_ghosts_periodic.restype = i
@@ -170,6 +172,20 @@ def conserved_sums(U, dh, sums_out=None, stream=None):
     _check("hydro_conserved_sums", lib().hydro_conserved_sums(_ptr(U), U.shape[0], float(dh), _dtype_flag(U),
                                                               _ptr(sums_out), _stream(stream)))
     return sums_out
+
+
+def cfl_dt_sums(U, dh, gamma, cfl, dt_out=None, sums_out=None, stream=None):
+    """FP64 dt and conserved sums of interiors U [n,5,16,16,16] in one pass
+    (bit-identical to cfl_dt and conserved_sums)."""
+    _require(U, "U")
+    if dt_out is None:
+        dt_out = torch.empty(1, dtype=torch.float64, device=U.device)
+    if sums_out is None:
+        sums_out = torch.empty(5, dtype=torch.float64, device=U.device)
+    _check("hydro_cfl_dt_sums", lib().hydro_cfl_dt_sums(_ptr(U), U.shape[0], float(dh), float(gamma), float(cfl),
+                                                        _dtype_flag(U), _ptr(dt_out), _ptr(sums_out),
+                                                        _stream(stream)))
+    return dt_out, sums_out
 
 
 def fill_ghosts_periodic(box, g, out=None, *, grouped=False, shape=None, stream=None):

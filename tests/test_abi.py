@@ -98,3 +98,14 @@ def test_set_launch_shape_validation():
     H.set_launch_shape(f64, 512, 2)
     H.set_launch_shape(ctu, 7, 2)
     H.set_launch_shape(ctu, 0, 4)  # back to the default variant
+
+
+def test_cfl_dt_sums_validation(L):
+    """Argument checks of the one-pass dt + sums (host only)."""
+    EINVAL, EALIAS = -1, -4
+    P = ctypes.c_void_p
+    assert L.hydro_cfl_dt_sums(P(0x1000), 0, 1.0, 1.4, 0.5, 0, P(0x2000), P(0x3000), None) == EINVAL
+    assert L.hydro_cfl_dt_sums(P(0), 4, 1.0, 1.4, 0.5, 0, P(0x2000), P(0x3000), None) == EINVAL
+    assert L.hydro_cfl_dt_sums(P(0x1000), 4, 1.0, 1.0, 0.5, 0, P(0x2000), P(0x3000), None) == EINVAL
+    assert L.hydro_cfl_dt_sums(P(0x1000), 4, 1.0, 1.4, 0.5, 0x100, P(0x2000), P(0x3000), None) == EINVAL
+    assert L.hydro_cfl_dt_sums(P(0x1000), 4, 1.0, 1.4, 0.5, 0, P(0x2000), P(0x2000 - 8), None) == EALIAS

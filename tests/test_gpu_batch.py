@@ -302,3 +302,25 @@ def test_diagnostic_counts_do_not_depend_on_launch_shape(H, case):
         assert first[key] > 0, (dtype, first)
         for shape, d in counts.items():
             assert d == first, (dtype, shape, d, first)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_cfl_dt_sums_bit_identical_to_separate_reductions(H, dtype):
+    """The one-pass dt + sums equals hydro_cfl_dt and hydro_conserved_sums
+    bit for bit, for group counts that leave ragged slices per workgroup."""
+    gamma = 1.4
+    rng = np.random.default_rng(44)
+    for n in (1, 7, 300, 1031):
+        rho = rng.uniform(0.5, 2.0, (n, 4096))
+        v = rng.normal(0.0, 0.7, (3, n, 4096))
+        p = rng.uniform(0.2, 3.0, (n, 4096))
+        U = np.stack([rho, rho * v[0], rho * v[1], rho * v[2],
+                      p / (gamma - 1) + 0.5 * rho * (v ** 2).sum(0)], axis=1).reshape(n, 5, 16, 16, 16)
+        Ut = _dev(U, dtype)
+        dh = 1.0 / 96
+        dt1 = H.cfl_dt(Ut, dh, gamma, 0.45)
+        s1 = H.conserved_sums(Ut, dh)
+        dt2, s2 = H.cfl_dt_sums(Ut, dh, gamma, 0.45)
+        torch.cuda.synchronize()
+        assert torch.equal(dt1, dt2), (n, dt1.item(), dt2.item())
+        assert torch.equal(s1, s2), (n, s1, s2)
