@@ -99,8 +99,9 @@ def traffic_from_profile(kernel_src_hash: str):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("fused_ctu.hpp", "fused_common.hpp", "hydro_math.hpp", "fused_ctu_f32.hip"):
-        with open(os.path.join(ROOT, "paper_1103_3373_amd", "csrc", f), "rb") as fh:
+    for f in ("csrc/fused_ctu.hpp", "csrc/fused_common.hpp", "csrc/hydro_math.hpp", "csrc/fused_ctu_f32.hip",
+              "build.py"):
+        with open(os.path.join(ROOT, "paper_1103_3373_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
