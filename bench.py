@@ -403,8 +403,8 @@ def side_measurements(args, H, W, state, nxt, dt_dev, n, gamma, dh, stream):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU runs are not part of "
-              "this build.", file=sys.stderr)
+        print(f"bench.py measures one GPU (asked for --gpus {args.gpus}): the solver library has no multi-GPU "
+              "path; patch groups would shard by domain decomposition with a halo exchange.", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1103_3373_amd import hydro as H

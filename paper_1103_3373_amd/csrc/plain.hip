@@ -3,7 +3,7 @@
 //
 //  * one workgroup per patch group (a grid-stride loop over groups);
 //  * every stage is a flattened 1D loop over the cells of its range with
-//    integer div/mod index recovery (Sec. 3.1 listing);
+//    integer div/mod index recovery, as the paper describes (Sec. 3.1);
 //  * intermediates (primitive variables, face states, fluxes) live in
 //    per-workgroup global temporaries that never leave the device (Sec. 3.1);
 //  * stages are separated by workgroup barriers.

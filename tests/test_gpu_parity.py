@@ -79,7 +79,7 @@ def test_fp64_limiters(H, lim, scheme, recon, char):
 
 @pytest.mark.parametrize("scheme,recon,rs,char", [(0, 0, 0, False), (1, 1, 1, True), (2, 1, 1, True),
                                                   (2, 0, 2, False)])
-def test_fp64_ten_steps_c1_sod(H, scheme, recon, rs, char):
+def test_fp64_ten_steps_sod_32(H, scheme, recon, rs, char):
     """Sod along x with seeded density noise, 32^3 periodic box as 8 groups,
     gamma 5/3, CFL 0.5, FP64 plain path, 10 steps.
 

@@ -59,7 +59,7 @@ def _random_smooth_box(n, gamma, seed, amp=0.2, ny=None, nz=None):
 
 
 # ---------------------------------------------------------------------------
-# P1: exact Riemann solver
+# Exact Riemann solver
 # ---------------------------------------------------------------------------
 def test_exact_sod_matches_published_table(oracle):
     g = _golden("sod_exact_toro.txt")
@@ -109,7 +109,7 @@ def test_exact_riemann_symmetric_and_trivial(oracle):
 
 
 # ---------------------------------------------------------------------------
-# P8: Riemann solver consistency
+# Riemann solver consistency
 # ---------------------------------------------------------------------------
 def _phys_flux_x(Wp, gamma):
     r, u, v, w, p = Wp
@@ -157,7 +157,7 @@ def test_riemann_matches_exact_on_weak_jumps(oracle):
 
 
 # ---------------------------------------------------------------------------
-# P12 / P13: Roe failure and HLLE positivity (paper Sec. 2)
+# Roe failure and HLLE positivity (paper Sec. 2)
 # ---------------------------------------------------------------------------
 def test_roe_fails_on_strong_double_rarefaction(oracle):
     L, R = [1.0, -2.0, 0, 0, 0.4], [1.0, 2.0, 0, 0, 0.4]
@@ -207,7 +207,7 @@ def test_schemes_positive_and_fallback_counted_on_double_rarefaction(oracle, sch
 
 
 # ---------------------------------------------------------------------------
-# P9 / P10 / P11: limiters, PPM edges, characteristic decomposition
+# Limiters, PPM edges, characteristic decomposition
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("lim", LIMITERS)
 def test_limiter_identities(oracle, lim):
@@ -286,7 +286,7 @@ def test_riemann_solves_per_cell(oracle, scheme, per_cell):
 
 
 # ---------------------------------------------------------------------------
-# P2 conservation, P3 free stream, P4 contact, P5 1D reduction
+# Conservation, free stream, contact, 1D reduction
 # ---------------------------------------------------------------------------
 ALL_COMBOS = list(itertools.product(SCHEMES, RECONS, SOLVERS, (0, CHAR)))
 
@@ -341,7 +341,7 @@ def test_one_dimensional_reduction(oracle, scheme, recon):
 
 
 # ---------------------------------------------------------------------------
-# P6: symmetry (paper Sec. 1)
+# Symmetry (paper Sec. 1)
 # ---------------------------------------------------------------------------
 def _mirror_x(U):
     V = U[:, :, :, ::-1].copy()
@@ -379,7 +379,7 @@ def test_cycle_axes_is_a_rotation():
 
 
 # ---------------------------------------------------------------------------
-# P16: whole periodic box == patch-group decomposition with ghosts
+# Whole periodic box == patch-group decomposition with ghosts
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("scheme,recon", list(itertools.product(SCHEMES, RECONS)))
 def test_box_equals_group_decomposition(oracle, scheme, recon):
@@ -417,7 +417,7 @@ def test_group_mode_rejects_thin_ghosts(oracle):
 
 
 # ---------------------------------------------------------------------------
-# P7: second-order convergence on smooth linear waves
+# Second-order convergence on smooth linear waves
 # ---------------------------------------------------------------------------
 def _wave_error(oracle, scheme, recon, n, kvec, dims, cfl=0.4, gamma=5.0 / 3.0):
     U0, T = W.sound_wave_box(*dims(n), gamma=gamma, amp=1e-6, kvec=kvec)
@@ -444,7 +444,7 @@ def test_convergence_2d_oblique(oracle, scheme, recon):
 
 
 # ---------------------------------------------------------------------------
-# P1 on the schemes: Sod shock tube
+# The schemes on the Sod shock tube
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("scheme,recon,rs,flags", [c for c in ALL_COMBOS if c[2] != 2 or c[1] == 0])
 def test_sod_shock_position_and_plateau(oracle, scheme, recon, rs, flags):
@@ -542,7 +542,7 @@ def test_characteristic_limiting_reduces_oscillation(oracle):
 
 
 # ---------------------------------------------------------------------------
-# P14: linear amplification of the (pi,pi,pi) acoustic checkerboard
+# Linear amplification of the (pi,pi,pi) acoustic checkerboard
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("scheme,factor", [(0, lambda nu: 1 - 6 * nu), (1, lambda nu: 1 - 6 * nu + 18 * nu * nu)])
 def test_checkerboard_amplification(oracle, scheme, factor):
