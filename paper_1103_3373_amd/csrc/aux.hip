@@ -156,6 +156,7 @@ __global__ void __launch_bounds__(256) maxspeed_kernel(const T* __restrict__ U, 
   __shared__ double red[4];
   double m = 0.0;
   const long long total = n_blocks << 12;
+#pragma unroll 4
   for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
        t += (long long)gridDim.x * blockDim.x) {
     const T* u = U + ((t >> 12) * 5 << 12) + (t & 4095);
@@ -355,6 +356,9 @@ __global__ void __launch_bounds__(256) dtsums_kernel(const T* __restrict__ U, lo
   const long long lo = blockIdx.x * per, hi = min(total, lo + per);
   double s[5] = {0, 0, 0, 0, 0};
   double m = 0.0;
+  // Unrolled so that the FP64 division chains of several cells overlap; the
+  // sums still take the cells of a lane in order.
+#pragma unroll 4
   for (long long t = lo + threadIdx.x; t < hi; t += blockDim.x) {
     const T* u = U + ((t >> 12) * 5 << 12) + (t & 4095);
     double c[5];
