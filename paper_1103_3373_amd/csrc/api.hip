@@ -217,7 +217,7 @@ Tune tuned(int f64, int scheme, int recon, int riemann, int charlim, long long n
 template <typename T>
 int run_fused(const hy::Seg* segs_dev, int n_segs, long long n_groups, int g, int scheme, int recon, int riemann,
               int limiter, int flags, double gamma, unsigned long long* diag, int grid, int waves, hipStream_t st,
-              void* wstar, const hy::Seg* seg0 = nullptr, double dt0 = 0.0) {
+              void* wstar, const hy::Seg* seg0 = nullptr, double dt0 = 0.0, int wstar_box = 0) {
   hy::FusedArgs<T> a;
   a.segs = segs_dev;
   a.n_segs = n_segs;
@@ -235,6 +235,7 @@ int run_fused(const hy::Seg* segs_dev, int n_segs, long long n_groups, int g, in
   else memset(&a.seg0, 0, sizeof(a.seg0));
   a.dt0 = dt0;
   a.wstar = reinterpret_cast<T*>(wstar);
+  a.wstar_box = wstar_box;
   hy::FusedCfg cfg;
   cfg.grid = grid;
   cfg.waves = waves;
@@ -376,11 +377,12 @@ int hydro_step_box(const void* box_in, void* box_out, void* flux_out, int nx, in
   if (int rc = ensure_vl(w, (size_t)G * hy::fused_scratch_per_group(scheme, reconstruction) * esz)) return rc;
   // Passed by value: the kernel reads dt through seg.dt (segs == nullptr and
   // a device dt pointer in seg0).
+  // VL: the half step is computed once per cell of the box (wstar_box).
   if (f64)
     return run_fused<double>(nullptr, 1, G, g, scheme, reconstruction, riemann, limiter, flags, gamma, ds->diag,
-                             tu.grid, tu.waves, st, w.vl, &seg, -1.0);
+                             tu.grid, tu.waves, st, w.vl, &seg, -1.0, 1);
   return run_fused<float>(nullptr, 1, G, g, scheme, reconstruction, riemann, limiter, flags, gamma, ds->diag, tu.grid,
-                          tu.waves, st, w.vl, &seg, -1.0);
+                          tu.waves, st, w.vl, &seg, -1.0, 1);
 }
 
 int hydro_cfl_dt(const void* U, int n_groups, double dh, double gamma, double cfl, int flags, double* dt_out,

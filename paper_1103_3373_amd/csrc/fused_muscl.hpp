@@ -99,9 +99,17 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
     if (MODE == 0) {
       src.init(S, lg, col.x, col.y);
     } else {
-      Seg w{};
-      w.in = a.wstar;
-      src.init(&w, grp, col.x, col.y);
+      if (a.wstar_box) {
+        // W* of this segment is a grouped periodic box of the segment's
+        // shape: ghost cells come from the neighbouring groups.
+        Seg w = *S;
+        w.in = a.wstar + S->first * 5 * 4096;
+        src.init(&w, lg, col.x, col.y);
+      } else {
+        Seg w{};
+        w.in = a.wstar;
+        src.init(&w, grp, col.x, col.y);
+      }
       upd.init(S, lg, col.x, col.y);
     }
     auto wprim = [&](int z) -> V5<T> {

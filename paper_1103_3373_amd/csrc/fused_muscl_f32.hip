@@ -44,29 +44,33 @@ hipError_t launch_muscl_f32(const FusedArgs<float>& a, int mode, int recon, int 
   return mode == 0 ? launch_w<0, 2>(a, recon, riemann, cfg.grid, st) : launch_w<1, 2>(a, recon, riemann, cfg.grid, st);
 }
 
-template <bool PPM, int RS>
+template <int G, int RS>
 static hipError_t launch_pred(const FusedArgs<float>& a, int grid, hipStream_t st) {
-  auto k = vlpred::vl_predict_kernel<float, PPM, RS>;
-  const size_t shm = (size_t)vlpred::lds_elems<PPM>() * sizeof(float);
+  auto k = vlpred::vl_predict_kernel<float, G, RS>;
+  const size_t shm = (size_t)vlpred::lds_elems<G>() * sizeof(float);
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  k<<<dim3(grid), dim3(vlpred::kThreads), shm, st>>>(a);
+  k<<<dim3(grid), dim3(vlpred::threads<G>()), shm, st>>>(a);
   return hipGetLastError();
 }
 
+template <int G>
+static hipError_t launch_pred_g(const FusedArgs<float>& a, int riemann, int grid, hipStream_t st) {
+  if (riemann == 0) return launch_pred<G, 0>(a, grid, st);
+  if (riemann == 1) return launch_pred<G, 1>(a, grid, st);
+  return launch_pred<G, 2>(a, grid, st);
+}
+
+// Input ghost width of the predictor: the scheme's (PPM 4, PLM 3) for
+// ghosted groups, 1 when every segment is a periodic box (interiors only).
 hipError_t launch_vlpred_f32(const FusedArgs<float>& a, int recon, int riemann, int grid, hipStream_t st) {
-  if (recon == 1) {
-    if (riemann == 0) return launch_pred<true, 0>(a, grid, st);
-    if (riemann == 1) return launch_pred<true, 1>(a, grid, st);
-    return launch_pred<true, 2>(a, grid, st);
-  }
-  if (riemann == 0) return launch_pred<false, 0>(a, grid, st);
-  if (riemann == 1) return launch_pred<false, 1>(a, grid, st);
-  return launch_pred<false, 2>(a, grid, st);
+  if (a.wstar_box) return launch_pred_g<1>(a, riemann, grid, st);
+  if (recon == 1) return launch_pred_g<4>(a, riemann, grid, st);
+  return launch_pred_g<3>(a, riemann, grid, st);
 }
 
 }  // namespace hy

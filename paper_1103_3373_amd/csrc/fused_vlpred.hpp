@@ -1,9 +1,12 @@
 // First stage of the VL scheme (arXiv:1103.3373, Sec. 2): Riemann fluxes on
 // piecewise-constant data at every face, then the unsplit half step
 //   W* = W(U^n - dt/(2dh) sum_d (F1_{d,+} - F1_{d,-}))   (with floors)
-// on every cell that the second stage reconstructs from, i.e. the group
-// interior plus g-1 ghost layers.  W* goes to a scratch array laid out as
-// ghosted groups [group][5][N'][N'][N'], N' = 16 + 2(g-1).
+// on every cell that the second stage reconstructs from.  Two layouts:
+//  * ghosted groups (input ghost width G = g of the scheme): the interior
+//    plus G-1 ghost layers, [group][5][N'][N'][N'], N' = 16 + 2(G-1);
+//  * periodic boxes (G = 1): the interior only, [group][5][16][16][16], so
+//    every cell's W* is computed once and the second stage reads its ghost
+//    cells from the neighbouring groups of this grouped box.
 //
 // One workgroup per group marching along z; a thread per (x, y) column of
 // the padded input plane keeps U and W of planes z, z+1 and the z face flux
@@ -18,12 +21,13 @@ namespace vlpred {
 
 using namespace fz;
 
-constexpr int kThreads = 576;  // one thread per column of the 24 x 24 padded plane (PPM)
+// One thread per column of the padded input plane, rounded up to wavefronts.
+template <int G> constexpr int threads() { return ((16 + 2 * G) * (16 + 2 * G) + 63) / 64 * 64; }
 
-template <typename T, bool PPM, int RS>
-__global__ void __launch_bounds__(kThreads, 2) vl_predict_kernel(FusedArgs<T> a) {
-  constexpr int G = PPM ? 4 : 3;   // input ghost width
-  constexpr int N = 16 + 2 * G;
+template <typename T, int G, int RS>
+__global__ void __launch_bounds__(threads<G>(), 2) vl_predict_kernel(FusedArgs<T> a) {
+  constexpr int kThreads = threads<G>();
+  constexpr int N = 16 + 2 * G;   // G: input ghost width
   constexpr int Gs = G - 1;        // output ghost width
   constexpr int Ns = 16 + 2 * Gs;
   constexpr long NCs = (long)Ns * Ns * Ns;
@@ -119,8 +123,7 @@ __global__ void __launch_bounds__(kThreads, 2) vl_predict_kernel(FusedArgs<T> a)
   flush_diag(a, fails, floors);
 }
 
-template <bool PPM> constexpr int lds_elems() {
-  constexpr int G = PPM ? 4 : 3;
+template <int G> constexpr int lds_elems() {
   constexpr int N = 16 + 2 * G;
   constexpr int Ns = 16 + 2 * (G - 1);
   return 5 * N * N + 10 * (N - 1) * Ns;

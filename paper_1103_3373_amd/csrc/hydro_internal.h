@@ -54,8 +54,12 @@ struct FusedArgs {
   // (segs == nullptr), so no table upload is needed.
   Seg seg0;
   double dt0;
-  // VL: scratch for the half-step primitive state, [n_groups][5][N'^3].
+  // VL: scratch for the half-step primitive state.  wstar_box == 0: ghosted
+  // per group, [n_groups][5][N'^3]; wstar_box == 1 (every segment a periodic
+  // box): interiors only, [n_groups][5][16^3], each segment's part a grouped
+  // box of its own whose ghost cells the second stage reads from neighbours.
   T* wstar;
+  int wstar_box;
 };
 
 struct FusedCfg {

@@ -54,8 +54,18 @@ def test_step_box_equals_fill_and_solve(H, scheme, recon, rs, char, dtype):
     H.solve_groups(ghosted, out_ref, fl_ref, dt=dt, dh=1 / 48, gamma=gamma, scheme=scheme, recon=recon, riemann=rs,
                    char=char, flux_mid=True)
     torch.cuda.synchronize()
-    assert torch.equal(out_box, out_ref)
-    assert torch.equal(fl_box, fl_ref)
+    if scheme == 1:
+        # The box path computes the VL half step once per cell with the
+        # interiors-only predictor (a different kernel instantiation, whose
+        # compiled FMA contractions may differ in the last bit); the groups
+        # path uses the ghosted one.  Hold them to a few ulps.
+        tol = 4 * (2.0 ** -23 if dtype == torch.float32 else 2.0 ** -52)
+        scale = out_ref.abs().max()
+        assert ((out_box - out_ref).abs().max() / scale).item() <= tol
+        assert ((fl_box - fl_ref).abs().max() / fl_ref.abs().max()).item() <= tol
+    else:
+        assert torch.equal(out_box, out_ref)
+        assert torch.equal(fl_box, fl_ref)
     # and the oracle on the whole periodic box
     src = W.box_to_groups(box) if dtype == torch.float64 else W.box_to_groups(box).astype(np.float32)
     ref = O.step_box(W.groups_to_box(src.astype(np.float64), nx, ny, nz), dt, 1 / 48, gamma, scheme, recon, rs, 1,
