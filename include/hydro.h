@@ -66,6 +66,7 @@ enum hydro_limiter { HYDRO_LIM_GMINMOD = 0, HYDRO_LIM_VANLEER = 1, HYDRO_LIM_VAN
 #define HYDRO_PLAIN 0x08        /* plain per-group path (Sec. 3.1 design); default: fused path */
 #define HYDRO_ROE_FB_HLLC 0x10  /* Roe fallback flux = HLLC (default HLLE) */
 #define HYDRO_BOX_GROUPED 0x20  /* hydro_fill_ghosts_periodic: box is [G][5][16][16][16] */
+#define HYDRO_BOX_SEGS 0x40     /* hydro_solve_batch: every segment is a periodic box (box == 1) */
 
 /* error codes */
 #define HYDRO_OK 0
@@ -211,6 +212,10 @@ struct hydro_spec {
  */
 int hydro_solve_batch(const struct hydro_seg* segs, int n_segs, long long n_groups_total,
                       const struct hydro_spec* spec, void* stream);
+/* With HYDRO_BOX_SEGS in spec->flags the caller asserts that every segment
+ * is a periodic box; VL then computes its half step once per cell instead of
+ * once per ghosted group.  A launch whose table contradicts the flag writes
+ * NaN to the outputs of the offending segments. */
 
 /*
  * Autotuner: times the fused kernel's launch shapes for `spec` on a

@@ -30,7 +30,8 @@ int hip_fail(hipError_t e, const char* what) {
   return fail(HYDRO_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-const int kKnownFlags = HYDRO_F64 | HYDRO_CHAR | HYDRO_FLUX_MID | HYDRO_PLAIN | HYDRO_ROE_FB_HLLC | HYDRO_BOX_GROUPED;
+const int kKnownFlags =
+    HYDRO_F64 | HYDRO_CHAR | HYDRO_FLUX_MID | HYDRO_PLAIN | HYDRO_ROE_FB_HLLC | HYDRO_BOX_GROUPED | HYDRO_BOX_SEGS;
 
 int ghost_width(int scheme, int recon) {
   if (scheme < 0 || scheme > 2 || recon < 0 || recon > 1) return -1;
@@ -336,11 +337,14 @@ int hydro_solve_batch(const struct hydro_seg* segs, int n_segs, long long n_grou
                                 (f64 ? 8 : 4)))
     return rc;
   const hy::Seg* sd = (const hy::Seg*)segs;
+  const int box_segs = (spec->flags & HYDRO_BOX_SEGS) ? 1 : 0;
   if (f64)
     return run_fused<double>(sd, n_segs, n_groups_total, g, spec->scheme, spec->reconstruction, spec->riemann,
-                             spec->limiter, spec->flags, spec->gamma, ds->diag, tu.grid, tu.waves, st, w.vl);
+                             spec->limiter, spec->flags, spec->gamma, ds->diag, tu.grid, tu.waves, st, w.vl, nullptr,
+                             0.0, box_segs);
   return run_fused<float>(sd, n_segs, n_groups_total, g, spec->scheme, spec->reconstruction, spec->riemann,
-                          spec->limiter, spec->flags, spec->gamma, ds->diag, tu.grid, tu.waves, st, w.vl);
+                          spec->limiter, spec->flags, spec->gamma, ds->diag, tu.grid, tu.waves, st, w.vl, nullptr, 0.0,
+                          box_segs);
 }
 
 int hydro_step_box(const void* box_in, void* box_out, void* flux_out, int nx, int ny, int nz, const double* dt_dev,

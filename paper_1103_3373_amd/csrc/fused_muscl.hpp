@@ -90,6 +90,9 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
     T* __restrict__ FO = S->flux ? reinterpret_cast<T*>(S->flux) + lg * 3 * a.nf * 5 * 256 : nullptr;
     ph.dtdh = (T)(dt / S->dh);
     ph.hdtdh = (T)(0.5 * dt / S->dh);
+    // A segment that is no box in a launch that declared boxes only: its
+    // half step was not computed for it, so its output is made NaN.
+    const T poison = (MODE == 1 && a.wstar_box && !S->box) ? __builtin_nan("") : T(0);
 
     // Sources: MHM reads U^n (ghost width G) and converts; VL reads the
     // half-step primitive W* from the predictor's scratch (ghost width G)
@@ -296,7 +299,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
           V5<T> u = ucons(t - 1);
           const int o = ((t - 1) * 16 + y) * 16 + x;
 #pragma unroll
-          for (int n = 0; n < 5; ++n) O[n * 4096 + o] = u[n] - ph.dtdh * (acc[n] + hn[n]);
+          for (int n = 0; n < 5; ++n) O[n * 4096 + o] = u[n] - ph.dtdh * (acc[n] + hn[n]) + poison;
         }
         if (t >= 0 && t <= 15) {
           V5<T> fx = sub5(lds5(sF2, kF2, y * 17 + x + 1), lds5(sF2, kF2, y * 17 + x));

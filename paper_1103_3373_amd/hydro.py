@@ -19,7 +19,7 @@ MHM, VL, CTU = 0, 1, 2
 PLM, PPM = 0, 1
 ROE, HLLC, HLLE = 0, 1, 2
 GMINMOD, VANLEER, VANALBADA, HYBRID = 0, 1, 2, 3
-F64, CHAR, FLUX_MID, PLAIN, ROE_FB_HLLC, BOX_GROUPED = 0x01, 0x02, 0x04, 0x08, 0x10, 0x20
+F64, CHAR, FLUX_MID, PLAIN, ROE_FB_HLLC, BOX_GROUPED, BOX_SEGS = 0x01, 0x02, 0x04, 0x08, 0x10, 0x20, 0x40
 
 EXPORTS = (
     "hydro_ghost_width", "hydro_solve_groups", "hydro_cfl_dt", "hydro_conserved_sums", "hydro_cfl_dt_sums",
@@ -223,9 +223,10 @@ def fill_groups_interp(coarse, layout, g, base_dh, out=None, stream=None):
 
 
 def make_spec(scheme, recon, riemann, limiter=VANLEER, *, gamma, char=False, f64=False, flux_mid=False,
-              roe_fb_hllc=False) -> Spec:
+              roe_fb_hllc=False, box_segs=False) -> Spec:
+    """box_segs: the batch's segments are all periodic boxes (HYDRO_BOX_SEGS)."""
     flags = (F64 if f64 else 0) | (CHAR if char else 0) | (FLUX_MID if flux_mid else 0) \
-        | (ROE_FB_HLLC if roe_fb_hllc else 0)
+        | (ROE_FB_HLLC if roe_fb_hllc else 0) | (BOX_SEGS if box_segs else 0)
     return Spec(scheme, recon, riemann, limiter, flags, float(gamma))
 
 

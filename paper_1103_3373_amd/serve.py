@@ -281,8 +281,10 @@ class GpuBackend:
     def _spec(self, scheme, riemann):
         key = (scheme, riemann)
         if key not in self.specs:
+            # Every simulation is a periodic box segment: VL computes its
+            # half step once per cell.
             self.specs[key] = self.H.make_spec(scheme, self.recon, riemann, self.limiter, gamma=self.gamma,
-                                               char=self.char)
+                                               char=self.char, box_segs=True)
         return self.specs[key]
 
     def tick(self, handles):

@@ -334,3 +334,50 @@ def test_cfl_dt_sums_bit_identical_to_separate_reductions(H, dtype):
         torch.cuda.synchronize()
         assert torch.equal(dt1, dt2), (n, dt1.item(), dt2.item())
         assert torch.equal(s1, s2), (n, s1, s2)
+
+
+def test_vl_box_segments_in_one_launch(H):
+    """VL over two periodic boxes of different shapes in one launch: declared
+    as boxes (half step once per cell) it equals each box stepped alone bit
+    for bit; undeclared (ghosted half step) it agrees to a few ulps; and a
+    ghosted-groups segment in a launch declared as boxes comes out NaN while
+    the box segment beside it stays finite."""
+    gamma = 1.4
+    shapes = ((32, 32, 32), (48, 32, 16))
+    boxes = [W.lognormal_blast_box(48, gamma=gamma, seed=31 + k, radius_cells=3)[:, :nz, :ny, :nx].copy()
+             for k, (nx, ny, nz) in enumerate(shapes)]
+    B = [_dev(W.box_to_groups(b), torch.float32) for b in boxes]
+    dt_dev = torch.tensor([1.2e-3], dtype=torch.float64, device="cuda")
+    kw = dict(gamma=gamma, scheme=H.VL, recon=H.PPM, riemann=H.HLLC, char=True)
+    alone = []
+    for b, (nx, ny, nz) in zip(B, shapes):
+        o = torch.empty_like(b)
+        H.step_box(b, o, (nx, ny, nz), dt_dev, dh=1 / 48, **kw)
+        alone.append(o)
+    n = sum(b.shape[0] for b in B)
+    for declared in (True, False):
+        outs = [torch.empty_like(b) for b in B]
+        rows, first = [], 0
+        for b, o, (nx, ny, nz) in zip(B, outs, shapes):
+            rows.append((b, o, None, dt_dev, 1.0, 1 / 48, first, b.shape[0], (nx // 16, ny // 16, nz // 16)))
+            first += b.shape[0]
+        spec = H.make_spec(H.VL, H.PPM, H.HLLC, gamma=gamma, char=True, box_segs=declared)
+        H.solve_batch(H.seg_table(rows, "cuda"), len(rows), n, spec)
+        torch.cuda.synchronize()
+        for o, a in zip(outs, alone):
+            if declared:
+                assert torch.equal(o, a)
+            else:
+                assert ((o - a).abs().max() / a.abs().max()).item() <= 4 * 2.0 ** -23
+    # A ghosted segment under the box declaration is flagged with NaN.
+    g = H.ghost_width(H.VL, H.PPM)
+    nx, ny, nz = shapes[0]
+    Gh = H.fill_ghosts_periodic(B[0], g, grouped=True, shape=(nx, ny, nz))
+    o0, o1 = torch.empty_like(B[0]), torch.empty_like(B[1])
+    rows = [(B[1], o1, None, dt_dev, 1.0, 1 / 48, 0, B[1].shape[0], (3, 2, 1)),
+            (Gh, o0, None, dt_dev, 1.0, 1 / 48, B[1].shape[0], Gh.shape[0])]
+    spec = H.make_spec(H.VL, H.PPM, H.HLLC, gamma=gamma, char=True, box_segs=True)
+    H.solve_batch(H.seg_table(rows, "cuda"), len(rows), B[1].shape[0] + Gh.shape[0], spec)
+    torch.cuda.synchronize()
+    assert torch.isnan(o0).all()
+    assert torch.equal(o1, alone[1])
