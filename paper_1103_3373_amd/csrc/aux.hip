@@ -114,12 +114,86 @@ __global__ void __launch_bounds__(256) fill_interp_kernel(const T* __restrict__ 
   }
 }
 
+// The same interpolation with one workgroup per (group, z plane) and the
+// ghost width fixed at compile time: the level, the z weights and the coarse
+// z indices are uniform over the workgroup, the in-plane indices need no
+// division by a run-time value, and the coarse indices wrap by addition.
+// The floating-point expressions are those of fill_interp_kernel, evaluated
+// without contraction, so the values are those of a plain FP64 evaluation.
+__device__ __forceinline__ int wrap_index(long long v, int n) {
+  while (v < 0) v += n;
+  while (v >= n) v -= n;
+  return (int)v;
+}
+template <typename T, int G>
+__global__ void __launch_bounds__(256) fill_interp_plane_kernel(const T* __restrict__ coarse, int cn,
+                                                                const int4* __restrict__ layout, double base_dh,
+                                                                T* __restrict__ out, long long g0) {
+#pragma clang fp contract(off)
+  constexpr int N = 16 + 2 * G;
+  constexpr long long nc = (long long)N * N * N;
+  const long long cc = (long long)cn * cn * cn;
+  const int k = blockIdx.x;
+  const long long grp = g0 + blockIdx.y;
+  const int4 L = layout[grp];
+  const double dh = base_dh / (double)(1 << L.x);
+  const double Z = ((double)(L.w + k - G) + 0.5) * dh * cn - 0.5;
+  const double fz0 = floor(Z);
+  const double az = Z - fz0;
+  const int z0 = wrap_index((long long)fz0, cn), z1 = z0 + 1 == cn ? 0 : z0 + 1;
+  T* o = out + grp * 5 * nc + (long long)k * N * N;
+  for (int r = threadIdx.x; r < N * N; r += blockDim.x) {
+    const int i = r % N, j = r / N;
+    const double X = ((double)(L.y + i - G) + 0.5) * dh * cn - 0.5;
+    const double Y = ((double)(L.z + j - G) + 0.5) * dh * cn - 0.5;
+    const double fx0 = floor(X), fy0 = floor(Y);
+    const double ax = X - fx0, ay = Y - fy0;
+    const int x0 = wrap_index((long long)fx0, cn), y0 = wrap_index((long long)fy0, cn);
+    const int x1 = x0 + 1 == cn ? 0 : x0 + 1, y1 = y0 + 1 == cn ? 0 : y0 + 1;
+    const long long c000 = ((long long)z0 * cn + y0) * cn + x0, c001 = ((long long)z0 * cn + y0) * cn + x1;
+    const long long c010 = ((long long)z0 * cn + y1) * cn + x0, c011 = ((long long)z0 * cn + y1) * cn + x1;
+    const long long c100 = ((long long)z1 * cn + y0) * cn + x0, c101 = ((long long)z1 * cn + y0) * cn + x1;
+    const long long c110 = ((long long)z1 * cn + y1) * cn + x0, c111 = ((long long)z1 * cn + y1) * cn + x1;
+#pragma unroll
+    for (int n = 0; n < 5; ++n) {
+      const T* f = coarse + n * cc;
+      const double v00 = (1.0 - ax) * (double)f[c000] + ax * (double)f[c001];
+      const double v01 = (1.0 - ax) * (double)f[c010] + ax * (double)f[c011];
+      const double v10 = (1.0 - ax) * (double)f[c100] + ax * (double)f[c101];
+      const double v11 = (1.0 - ax) * (double)f[c110] + ax * (double)f[c111];
+      const double v0 = (1.0 - ay) * v00 + ay * v01;
+      const double v1 = (1.0 - ay) * v10 + ay * v11;
+      o[n * nc + r] = (T)((1.0 - az) * v0 + az * v1);
+    }
+  }
+}
+
+template <typename T, int G>
+static hipError_t launch_interp_planes(const T* coarse, int cn, const int* layout, long long n_groups, double base_dh,
+                                       T* out, hipStream_t st) {
+  constexpr int N = 16 + 2 * G;
+  for (long long g0 = 0; g0 < n_groups; g0 += 65535) {
+    const long long chunk = n_groups - g0 < 65535 ? n_groups - g0 : 65535;
+    fill_interp_plane_kernel<T, G><<<dim3(N, (unsigned)chunk), dim3(256), 0, st>>>(coarse, cn, (const int4*)layout,
+                                                                                   base_dh, out, g0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 template <typename T>
 hipError_t launch_fill_interp(const T* coarse, int cn, const int* layout, long long n_groups, int g, double base_dh,
                               T* out, hipStream_t st) {
   const int N = 16 + 2 * g;
   const long long total = n_groups * N * N * N;
   if (total == 0) return hipSuccess;
+  switch (g) {
+    case 2: return launch_interp_planes<T, 2>(coarse, cn, layout, n_groups, base_dh, out, st);
+    case 3: return launch_interp_planes<T, 3>(coarse, cn, layout, n_groups, base_dh, out, st);
+    case 4: return launch_interp_planes<T, 4>(coarse, cn, layout, n_groups, base_dh, out, st);
+    default: break;
+  }
   long long blocks = (total + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   fill_interp_kernel<T><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(coarse, cn, (const int4*)layout, g, base_dh,

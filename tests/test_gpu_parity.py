@@ -235,13 +235,18 @@ def test_periodic_ghost_fill_bit_exact(H, g):
     np.testing.assert_array_equal(got2, want)
 
 
-def test_interp_fill_matches_oracle(H):
+@pytest.mark.parametrize("g", [2, 3, 4, 5])
+def test_interp_fill_matches_oracle(H, g):
+    """Trilinear preparation of AMR-shaped groups against the oracle (which
+    sums the eight weighted corners; the kernels interpolate axis by axis,
+    so the FP64 results agree to rounding).  g = 5 takes the generic
+    kernel."""
     coarse = W.amr_coarse_field(16, seed=5)
     lay = W.amr_layout((3, 5, 7), base_n=32, seed=5)
-    want = O.fill_groups_interp(coarse, lay, 3, 1 / 32)
-    got = H.fill_groups_interp(_dev(coarse, torch.float64), torch.from_numpy(lay).cuda(), 3, 1 / 32).cpu().numpy()
+    want = O.fill_groups_interp(coarse, lay, g, 1 / 32)
+    got = H.fill_groups_interp(_dev(coarse, torch.float64), torch.from_numpy(lay).cuda(), g, 1 / 32).cpu().numpy()
     assert scaled_max_err(got, want) <= 1e-15
-    got32 = H.fill_groups_interp(_dev(coarse, torch.float32), torch.from_numpy(lay).cuda(), 3, 1 / 32).cpu().numpy()
+    got32 = H.fill_groups_interp(_dev(coarse, torch.float32), torch.from_numpy(lay).cuda(), g, 1 / 32).cpu().numpy()
     assert scaled_max_err(got32, want) <= 2e-7
 
 
