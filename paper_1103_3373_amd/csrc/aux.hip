@@ -15,11 +15,14 @@ namespace hy {
 // Source either a plain box [5][nz][ny][nx] or the grouped interior layout
 // [G][5][16][16][16] (grouped != 0).  One thread per output cell, x fastest.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(512) fill_periodic_kernel(const T* __restrict__ box, int nx, int ny, int nz, int g,
+// GC > 0: the ghost width fixed at compile time (no run-time integer
+// division per cell); GC == 0: g taken at run time.
+template <typename T, int GC>
+__global__ void __launch_bounds__(512) fill_periodic_kernel(const T* __restrict__ box, int nx, int ny, int nz, int g_rt,
                                                             int grouped, T* __restrict__ out, long long g_off) {
   // blockIdx.x = plane k of the padded group, blockIdx.y = group; threads
   // cover the N x N plane, x fastest (coalesced writes).
+  const int g = GC > 0 ? GC : g_rt;
   const int N = 16 + 2 * g;
   const long long nc = (long long)N * N * N;
   const int k = blockIdx.x;
@@ -57,7 +60,13 @@ hipError_t launch_fill_periodic(const T* box, int nx, int ny, int nz, int g, int
   // grid.y is limited to 65535 groups per launch.
   for (long long g0 = 0; g0 < groups; g0 += 65535) {
     const long long cnt = groups - g0 < 65535 ? groups - g0 : 65535;
-    fill_periodic_kernel<T><<<dim3(N, (unsigned)cnt), dim3(512), 0, st>>>(box, nx, ny, nz, g, grouped, out, g0);
+    const dim3 grid(N, (unsigned)cnt);
+    switch (g) {
+      case 2: fill_periodic_kernel<T, 2><<<grid, dim3(512), 0, st>>>(box, nx, ny, nz, g, grouped, out, g0); break;
+      case 3: fill_periodic_kernel<T, 3><<<grid, dim3(512), 0, st>>>(box, nx, ny, nz, g, grouped, out, g0); break;
+      case 4: fill_periodic_kernel<T, 4><<<grid, dim3(512), 0, st>>>(box, nx, ny, nz, g, grouped, out, g0); break;
+      default: fill_periodic_kernel<T, 0><<<grid, dim3(512), 0, st>>>(box, nx, ny, nz, g, grouped, out, g0); break;
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -223,7 +223,7 @@ def test_conserved_sums(H):
     assert want.shape == (5,)
 
 
-@pytest.mark.parametrize("g", [2, 3, 4])
+@pytest.mark.parametrize("g", [2, 3, 4, 5])
 def test_periodic_ghost_fill_bit_exact(H, g):
     rng = np.random.default_rng(g)
     box = rng.standard_normal((5, 32, 48, 16))
