@@ -123,72 +123,81 @@ __global__ void __launch_bounds__(256) fill_interp_kernel(const T* __restrict__ 
   }
 }
 
-// The same interpolation with one workgroup per (group, z plane) and the
-// ghost width fixed at compile time: the level, the z weights and the coarse
-// z indices are uniform over the workgroup, the in-plane indices need no
-// division by a run-time value, and the coarse indices wrap by addition.
-// The floating-point expressions are those of fill_interp_kernel, evaluated
-// without contraction, so the values are those of a plain FP64 evaluation.
+// The same interpolation with one workgroup per group and one thread per
+// (x, y) column of its padded region, the ghost width fixed at compile time.
+// A column's x and y weights and coarse indices are formed once.  Along z,
+// the value of a fine cell is the z blend of the x-y interpolations at the
+// two coarse layers that bracket it.  Where the fine level is finer than the
+// coarse field, the pair stays the same over several consecutive fine planes
+// and moves by one layer at a time, so each thread keeps both layers' x-y
+// values in registers and reads the coarse field only for a new layer.
+// Every value is formed by the expressions of fill_interp_kernel, in the
+// same order and without contraction, so the results are those of a plain
+// FP64 evaluation.
 __device__ __forceinline__ int wrap_index(long long v, int n) {
-  while (v < 0) v += n;
-  while (v >= n) v -= n;
+  if (v < 0 || v >= n) {  // ghost cells across the periodic boundary
+    v %= n;
+    if (v < 0) v += n;
+  }
   return (int)v;
 }
+template <int G> constexpr int interp_threads() { return ((16 + 2 * G) * (16 + 2 * G) + 63) / 64 * 64; }
+
 template <typename T, int G>
-__global__ void __launch_bounds__(256) fill_interp_plane_kernel(const T* __restrict__ coarse, int cn,
-                                                                const int4* __restrict__ layout, double base_dh,
-                                                                T* __restrict__ out, long long g0) {
+__global__ void __launch_bounds__(interp_threads<G>()) fill_interp_group_kernel(const T* __restrict__ coarse, int cn,
+                                                                               const int4* __restrict__ layout,
+                                                                               double base_dh, T* __restrict__ out) {
 #pragma clang fp contract(off)
   constexpr int N = 16 + 2 * G;
   constexpr long long nc = (long long)N * N * N;
   const long long cc = (long long)cn * cn * cn;
-  const int k = blockIdx.x;
-  const long long grp = g0 + blockIdx.y;
+  const long long grp = blockIdx.x;
   const int4 L = layout[grp];
   const double dh = base_dh / (double)(1 << L.x);
-  const double Z = ((double)(L.w + k - G) + 0.5) * dh * cn - 0.5;
-  const double fz0 = floor(Z);
-  const double az = Z - fz0;
-  const int z0 = wrap_index((long long)fz0, cn), z1 = z0 + 1 == cn ? 0 : z0 + 1;
-  T* o = out + grp * 5 * nc + (long long)k * N * N;
-  for (int r = threadIdx.x; r < N * N; r += blockDim.x) {
-    const int i = r % N, j = r / N;
-    const double X = ((double)(L.y + i - G) + 0.5) * dh * cn - 0.5;
-    const double Y = ((double)(L.z + j - G) + 0.5) * dh * cn - 0.5;
-    const double fx0 = floor(X), fy0 = floor(Y);
-    const double ax = X - fx0, ay = Y - fy0;
-    const int x0 = wrap_index((long long)fx0, cn), y0 = wrap_index((long long)fy0, cn);
-    const int x1 = x0 + 1 == cn ? 0 : x0 + 1, y1 = y0 + 1 == cn ? 0 : y0 + 1;
-    const long long c000 = ((long long)z0 * cn + y0) * cn + x0, c001 = ((long long)z0 * cn + y0) * cn + x1;
-    const long long c010 = ((long long)z0 * cn + y1) * cn + x0, c011 = ((long long)z0 * cn + y1) * cn + x1;
-    const long long c100 = ((long long)z1 * cn + y0) * cn + x0, c101 = ((long long)z1 * cn + y0) * cn + x1;
-    const long long c110 = ((long long)z1 * cn + y1) * cn + x0, c111 = ((long long)z1 * cn + y1) * cn + x1;
+  const int r = threadIdx.x;
+  if (r >= N * N) return;  // no barrier below
+  const int i = r % N, j = r / N;
+  const double X = ((double)(L.y + i - G) + 0.5) * dh * cn - 0.5;
+  const double Y = ((double)(L.z + j - G) + 0.5) * dh * cn - 0.5;
+  const double fx0 = floor(X), fy0 = floor(Y);
+  const double ax = X - fx0, ay = Y - fy0;
+  const int x0 = wrap_index((long long)fx0, cn), y0 = wrap_index((long long)fy0, cn);
+  const int x1 = x0 + 1 == cn ? 0 : x0 + 1, y1 = y0 + 1 == cn ? 0 : y0 + 1;
+  // x-y interpolation of layer z of variable n at this column.
+  auto layer = [&](int z, int n) -> double {
+    const T* f = coarse + n * cc + (long long)z * cn * cn;
+    const double v00 = (1.0 - ax) * (double)f[y0 * cn + x0] + ax * (double)f[y0 * cn + x1];
+    const double v01 = (1.0 - ax) * (double)f[y1 * cn + x0] + ax * (double)f[y1 * cn + x1];
+    return (1.0 - ay) * v00 + ay * v01;
+  };
+  T* o = out + grp * 5 * nc + r;
+  double v0[5], v1[5];
+  int zc = -1;  // coarse layer of v0 (none yet)
+  for (int k = 0; k < N; ++k) {
+    const double Z = ((double)(L.w + k - G) + 0.5) * dh * cn - 0.5;
+    const double fz0 = floor(Z);
+    const double az = Z - fz0;
+    const int z0 = wrap_index((long long)fz0, cn), z1 = z0 + 1 == cn ? 0 : z0 + 1;
+    if (z0 != zc) {  // uniform over the workgroup
+      const bool shift = zc >= 0 && z0 == (zc + 1 == cn ? 0 : zc + 1);
 #pragma unroll
-    for (int n = 0; n < 5; ++n) {
-      const T* f = coarse + n * cc;
-      const double v00 = (1.0 - ax) * (double)f[c000] + ax * (double)f[c001];
-      const double v01 = (1.0 - ax) * (double)f[c010] + ax * (double)f[c011];
-      const double v10 = (1.0 - ax) * (double)f[c100] + ax * (double)f[c101];
-      const double v11 = (1.0 - ax) * (double)f[c110] + ax * (double)f[c111];
-      const double v0 = (1.0 - ay) * v00 + ay * v01;
-      const double v1 = (1.0 - ay) * v10 + ay * v11;
-      o[n * nc + r] = (T)((1.0 - az) * v0 + az * v1);
+      for (int n = 0; n < 5; ++n) {
+        v0[n] = shift ? v1[n] : layer(z0, n);
+        v1[n] = layer(z1, n);
+      }
+      zc = z0;
     }
+#pragma unroll
+    for (int n = 0; n < 5; ++n) o[n * nc + (long long)k * N * N] = (T)((1.0 - az) * v0[n] + az * v1[n]);
   }
 }
 
 template <typename T, int G>
-static hipError_t launch_interp_planes(const T* coarse, int cn, const int* layout, long long n_groups, double base_dh,
+static hipError_t launch_interp_groups(const T* coarse, int cn, const int* layout, long long n_groups, double base_dh,
                                        T* out, hipStream_t st) {
-  constexpr int N = 16 + 2 * G;
-  for (long long g0 = 0; g0 < n_groups; g0 += 65535) {
-    const long long chunk = n_groups - g0 < 65535 ? n_groups - g0 : 65535;
-    fill_interp_plane_kernel<T, G><<<dim3(N, (unsigned)chunk), dim3(256), 0, st>>>(coarse, cn, (const int4*)layout,
-                                                                                   base_dh, out, g0);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  fill_interp_group_kernel<T, G><<<dim3((unsigned)n_groups), dim3(interp_threads<G>()), 0, st>>>(
+      coarse, cn, (const int4*)layout, base_dh, out);
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -198,9 +207,9 @@ hipError_t launch_fill_interp(const T* coarse, int cn, const int* layout, long l
   const long long total = n_groups * N * N * N;
   if (total == 0) return hipSuccess;
   switch (g) {
-    case 2: return launch_interp_planes<T, 2>(coarse, cn, layout, n_groups, base_dh, out, st);
-    case 3: return launch_interp_planes<T, 3>(coarse, cn, layout, n_groups, base_dh, out, st);
-    case 4: return launch_interp_planes<T, 4>(coarse, cn, layout, n_groups, base_dh, out, st);
+    case 2: return launch_interp_groups<T, 2>(coarse, cn, layout, n_groups, base_dh, out, st);
+    case 3: return launch_interp_groups<T, 3>(coarse, cn, layout, n_groups, base_dh, out, st);
+    case 4: return launch_interp_groups<T, 4>(coarse, cn, layout, n_groups, base_dh, out, st);
     default: break;
   }
   long long blocks = (total + 255) / 256;

@@ -236,12 +236,16 @@ def test_periodic_ghost_fill_bit_exact(H, g):
 
 
 @pytest.mark.parametrize("g", [2, 3, 4, 5])
-def test_interp_fill_matches_oracle(H, g):
+@pytest.mark.parametrize("cn", [16, 64])
+def test_interp_fill_matches_oracle(H, g, cn):
     """Trilinear preparation of AMR-shaped groups against the oracle (which
     sums the eight weighted corners; the kernels interpolate axis by axis,
     so the FP64 results agree to rounding).  g = 5 takes the generic
-    kernel."""
-    coarse = W.amr_coarse_field(16, seed=5)
+    kernel.  Levels of 32, 64 and 128 cells per side: the 16^3 coarse field
+    is coarser than all of them (coarse layers shared by fine planes); the
+    64^3 one is finer than level 0 (layers skipped), as fine as level 1 (a
+    new layer every plane) and coarser than level 2."""
+    coarse = W.amr_coarse_field(cn, seed=5)
     lay = W.amr_layout((3, 5, 7), base_n=32, seed=5)
     want = O.fill_groups_interp(coarse, lay, g, 1 / 32)
     got = H.fill_groups_interp(_dev(coarse, torch.float64), torch.from_numpy(lay).cuda(), g, 1 / 32).cpu().numpy()
