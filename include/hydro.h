@@ -133,7 +133,8 @@ int hydro_cfl_dt_sums(const void* U, int n_groups, double dh, double gamma, doub
  * Preparation step (Sec. 4.2), periodic box: build the ghosted groups
  * [G][5][N][N][N] (N = 16 + 2g, G = (gz*ngy + gy)*ngx + gx) from a box
  * [5][nz][ny][nx] (or [G][5][16][16][16] with HYDRO_BOX_GROUPED).  nx, ny,
- * nz must be positive multiples of 16; 0 <= g <= 16.
+ * nz must be positive multiples of 16 with fewer than 2^31 groups;
+ * 0 <= g <= 16 (else HYDRO_EINVAL).
  */
 int hydro_fill_ghosts_periodic(const void* box, int nx, int ny, int nz, int g, int flags, void* groups_out,
                                void* stream);

@@ -491,6 +491,7 @@ int hydro_fill_ghosts_periodic(const void* box, int nx, int ny, int nz, int g, i
     return fail(HYDRO_EINVAL, "box sizes must be positive multiples of 16");
   if (g < 0 || g > 16) return fail(HYDRO_EINVAL, "ghost width out of range");
   if (flags & ~kKnownFlags) return fail(HYDRO_EINVAL, "unknown flag bits");
+  if ((long long)(nx / 16) * (ny / 16) * (nz / 16) >= (1LL << 31)) return fail(HYDRO_EINVAL, "2^31 or more groups");
   const size_t esz = (flags & HYDRO_F64) ? 8 : 4;
   const size_t N = 16 + 2 * g;
   const size_t nb = (size_t)nx * ny * nz * 5 * esz;

@@ -20,34 +20,51 @@ namespace hy {
 template <typename T, int GC>
 __global__ void __launch_bounds__(512) fill_periodic_kernel(const T* __restrict__ box, int nx, int ny, int nz, int g_rt,
                                                             int grouped, T* __restrict__ out, long long g_off) {
-  // blockIdx.x = plane k of the padded group, blockIdx.y = group; threads
-  // cover the N x N plane, x fastest (coalesced writes).
+  // blockIdx.x = k in 0 .. N/2-1: the workgroup fills planes k and k + N/2
+  // of the padded group (N = 16 + 2g is even), all ten loads of a thread
+  // issued before its stores; blockIdx.y = group; threads cover the N x N
+  // plane, x fastest (coalesced writes).  Group counts stay below 2^31 (the
+  // caller checks), so the group coordinates use 32-bit division.
   const int g = GC > 0 ? GC : g_rt;
   const int N = 16 + 2 * g;
   const long long nc = (long long)N * N * N;
+  const int H = N / 2;
   const int k = blockIdx.x;
-  const long long G = g_off + blockIdx.y;
-  const int ngx = nx >> 4, ngy = ny >> 4;
+  const unsigned G = (unsigned)(g_off + blockIdx.y);
+  const unsigned ngx = (unsigned)nx >> 4, ngy = (unsigned)ny >> 4;
   const long long boxc = (long long)nx * ny * nz;
-  const int gx = (int)(G % ngx), gy = (int)((G / ngx) % ngy), gz = (int)(G / ((long long)ngx * ngy));
-  int sz = gz * 16 + k - g;
-  sz += (sz < 0) ? nz : 0;
-  sz -= (sz >= nz) ? nz : 0;
-  T* o = out + G * 5 * nc + (long long)k * N * N;
+  const int gx = (int)(G % ngx), gy = (int)((G / ngx) % ngy), gz = (int)(G / ngx / ngy);
+  int sz0 = gz * 16 + k - g, sz1 = sz0 + H;
+  sz0 += (sz0 < 0) ? nz : 0;
+  sz0 -= (sz0 >= nz) ? nz : 0;
+  sz1 += (sz1 < 0) ? nz : 0;
+  sz1 -= (sz1 >= nz) ? nz : 0;
+  T* o = out + (long long)G * 5 * nc + (long long)k * N * N;
+  const long long oH = (long long)H * N * N;
   for (int r = threadIdx.x; r < N * N; r += blockDim.x) {
     const int i = r % N, j = r / N;
     int sx = gx * 16 + i - g, sy = gy * 16 + j - g;
     sx += (sx < 0) ? nx : 0; sx -= (sx >= nx) ? nx : 0;
     sy += (sy < 0) ? ny : 0; sy -= (sy >= ny) ? ny : 0;
+    T v0[5], v1[5];
     if (grouped) {
-      const long long sg = ((long long)(sz >> 4) * ngy + (sy >> 4)) * ngx + (sx >> 4);
-      const T* s = box + sg * 5 * 4096 + (((sz & 15) * 16 + (sy & 15)) * 16 + (sx & 15));
+      const long long base = ((long long)(sy >> 4) * ngx + (sx >> 4));
+      const long long sg0 = (long long)(sz0 >> 4) * ngy * ngx + base, sg1 = (long long)(sz1 >> 4) * ngy * ngx + base;
+      const int in = ((sy & 15) * 16 + (sx & 15));
+      const T* s0 = box + sg0 * 5 * 4096 + (sz0 & 15) * 256 + in;
+      const T* s1 = box + sg1 * 5 * 4096 + (sz1 & 15) * 256 + in;
 #pragma unroll
-      for (int n = 0; n < 5; ++n) o[n * nc + r] = s[n * 4096];
+      for (int n = 0; n < 5; ++n) { v0[n] = s0[n * 4096]; v1[n] = s1[n * 4096]; }
     } else {
-      const T* s = box + ((long long)sz * ny + sy) * nx + sx;
+      const T* s0 = box + ((long long)sz0 * ny + sy) * nx + sx;
+      const T* s1 = box + ((long long)sz1 * ny + sy) * nx + sx;
 #pragma unroll
-      for (int n = 0; n < 5; ++n) o[n * nc + r] = s[n * boxc];
+      for (int n = 0; n < 5; ++n) { v0[n] = s0[n * boxc]; v1[n] = s1[n * boxc]; }
+    }
+#pragma unroll
+    for (int n = 0; n < 5; ++n) {
+      o[n * nc + r] = v0[n];
+      o[n * nc + oH + r] = v1[n];
     }
   }
 }
@@ -60,7 +77,7 @@ hipError_t launch_fill_periodic(const T* box, int nx, int ny, int nz, int g, int
   // grid.y is limited to 65535 groups per launch.
   for (long long g0 = 0; g0 < groups; g0 += 65535) {
     const long long cnt = groups - g0 < 65535 ? groups - g0 : 65535;
-    const dim3 grid(N, (unsigned)cnt);
+    const dim3 grid(N / 2, (unsigned)cnt);
     switch (g) {
       case 2: fill_periodic_kernel<T, 2><<<grid, dim3(512), 0, st>>>(box, nx, ny, nz, g, grouped, out, g0); break;
       case 3: fill_periodic_kernel<T, 3><<<grid, dim3(512), 0, st>>>(box, nx, ny, nz, g, grouped, out, g0); break;
