@@ -7,12 +7,9 @@ template <bool PPM, int RS, int WAVES, bool FAST>
 static hipError_t launch_one(const FusedArgs<double>& a, int grid, hipStream_t st) {
   auto k = ctu::ctu_fused_kernel<double, PPM, RS, WAVES, FAST>;
   const size_t shm = ctu::kLdsBytes(sizeof(double));
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  static std::atomic<unsigned long long> lds_set{0};
+  const hipError_t e = raise_lds_limit((const void*)k, shm, lds_set);
+  if (e != hipSuccess) return e;
   k<<<dim3(grid), dim3(ctu::kThreads), shm, st>>>(a);
   return hipGetLastError();
 }

@@ -9,12 +9,9 @@ template <int MODE, bool PPM, int RS, int WAVES, bool FAST>
 static hipError_t launch_one(const FusedArgs<double>& a, int grid, hipStream_t st) {
   auto k = muscl::muscl_kernel<double, PPM, RS, WAVES, MODE, FAST>;
   const size_t shm = muscl::kLdsBytes(sizeof(double));
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  static std::atomic<unsigned long long> lds_set{0};
+  const hipError_t e = raise_lds_limit((const void*)k, shm, lds_set);
+  if (e != hipSuccess) return e;
   k<<<dim3(grid), dim3(fz::kThreads), shm, st>>>(a);
   return hipGetLastError();
 }
@@ -46,12 +43,9 @@ template <int G, int RS>
 static hipError_t launch_pred(const FusedArgs<double>& a, int grid, hipStream_t st) {
   auto k = vlpred::vl_predict_kernel<double, G, RS>;
   const size_t shm = (size_t)vlpred::lds_elems<G>() * sizeof(double);
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  static std::atomic<unsigned long long> lds_set{0};
+  const hipError_t e = raise_lds_limit((const void*)k, shm, lds_set);
+  if (e != hipSuccess) return e;
   k<<<dim3(grid), dim3(vlpred::threads<G>()), shm, st>>>(a);
   return hipGetLastError();
 }

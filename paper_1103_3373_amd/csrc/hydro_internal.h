@@ -4,9 +4,25 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "hydro_math.hpp"
 
 namespace hy {
+
+// Raises kernel fn's dynamic LDS limit to shm bytes on the current device,
+// once per device (device ids 0..63 are remembered in done; others are set
+// on every call).  done is one static per kernel instantiation.
+inline hipError_t raise_lds_limit(const void* fn, size_t shm, std::atomic<unsigned long long>& done) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const unsigned long long bit = (dev >= 0 && dev < 64) ? (1ull << dev) : 0ull;
+  if (bit && (done.load(std::memory_order_acquire) & bit)) return hipSuccess;
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  if (e == hipSuccess && bit) done.fetch_or(bit, std::memory_order_release);
+  return e;
+}
 
 template <typename T>
 struct PlainArgs {
