@@ -21,8 +21,12 @@ namespace vlpred {
 
 using namespace fz;
 
-// One thread per column of the padded input plane, rounded up to wavefronts.
-template <int G> constexpr int threads() { return ((16 + 2 * G) * (16 + 2 * G) + 63) / 64 * 64; }
+// Threads per workgroup.  Ghosted groups: one per column of the padded input
+// plane, rounded up to wavefronts.  Periodic boxes (G = 1): the faces of the
+// interior read only the interior columns and the one-cell ring beside its
+// four sides (not the four corner columns), so 320 threads: the interior
+// first (tid 0..255), then the ring.
+template <int G> constexpr int threads() { return G == 1 ? 320 : ((16 + 2 * G) * (16 + 2 * G) + 63) / 64 * 64; }
 
 template <typename T, int G, int RS>
 __global__ void __launch_bounds__(threads<G>(), 2) vl_predict_kernel(FusedArgs<T> a) {
@@ -39,9 +43,26 @@ __global__ void __launch_bounds__(threads<G>(), 2) vl_predict_kernel(FusedArgs<T
   T* sFY = sFX + 5 * nF;            // [5][nF]   index (j + G) * Ns + (x + Gs)
 
   const int tid = threadIdx.x;
-  const bool active = tid < N * N;
-  const int x = tid % N - G, y = tid / N - G;
-  const bool out_col = active && x >= -Gs && x <= 15 + Gs && y >= -Gs && y <= 15 + Gs;
+  int x, y;
+  bool active, out_col;
+  if constexpr (G == 1) {
+    if (tid < 256) {
+      x = tid & 15;
+      y = tid >> 4;
+    } else {  // the ring: x = -1, x = 16, y = -1, y = 16, 16 columns each
+      const int q = tid - 256, s = q & 15, side = q >> 4;
+      x = side == 0 ? -1 : (side == 1 ? 16 : s);
+      y = side == 2 ? -1 : (side == 3 ? 16 : s);
+    }
+    active = true;
+    out_col = tid < 256;
+  } else {
+    active = tid < N * N;
+    x = tid % N - G;
+    y = tid / N - G;
+    out_col = active && x >= -Gs && x <= 15 + Gs && y >= -Gs && y <= 15 + Gs;
+  }
+  const int pc = (y + G) * N + (x + G);  // the column's cell in the plane
   int fails = 0, floors = 0;
   Phys<T> ph = make_phys(a);
 
@@ -74,7 +95,7 @@ __global__ void __launch_bounds__(threads<G>(), 2) vl_predict_kernel(FusedArgs<T
       //         now and arrives while phases B and C run --------------------
       V5<T> hp;
       if (active) {
-        sts5(sP, N * N, tid, w0);
+        sts5(sP, N * N, pc, w0);
         u1 = unext;
         if (z + 2 <= 16 + Gs) unext = rd.load(z + 2);
         w1 = prim_of(u1, ph);
