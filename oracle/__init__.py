@@ -59,6 +59,8 @@ def _lib(counting: bool = False) -> ctypes.CDLL:
     L.oracle_fill_ghosts_periodic.restype = i
     L.oracle_fill_groups_interp.argtypes = [P, i, P, i, i, d, P]
     L.oracle_fill_groups_interp.restype = i
+    L.oracle_fill_groups_amr.argtypes = [P, P, i, i, i, P, P, i, P, i, P]
+    L.oracle_fill_groups_amr.restype = i
     L.oracle_cfl_dt.argtypes = [P, ctypes.c_long, ctypes.c_long, d, d, d]
     L.oracle_cfl_dt.restype = d
     L.oracle_conserved_sums.argtypes = [P, ctypes.c_long, ctypes.c_long, d, P]
@@ -156,6 +158,25 @@ def fill_groups_interp(coarse, layout, g, base_dh) -> np.ndarray:
     N = 16 + 2 * g
     out = np.empty((n, 5, N, N, N))
     _lib().oracle_fill_groups_interp(_p(coarse), coarse.shape[1], _p(layout), n, g, base_dh, _p(out))
+    return out
+
+
+def fill_groups_amr(fine, layout, ng0, alpha, coarse0, coarse1, g) -> np.ndarray:
+    """AMR preparation step (Sec. 4.2): padded groups [n][5][N]^3 from the
+    groups' own interiors fine [n][5][16]^3, same-level neighbours where they
+    cover a ghost cell, else the coarse pair blended at alpha[level] and
+    interpolated trilinearly; layout int32 [n][4] = (level, ox, oy, oz)."""
+    fine = _f64(fine)
+    c0, c1 = _f64(coarse0), _f64(coarse1)
+    layout = np.ascontiguousarray(layout, dtype=np.int32)
+    alpha = _f64(np.asarray(alpha, dtype=np.float64))
+    n = layout.shape[0]
+    N = 16 + 2 * g
+    out = np.empty((n, 5, N, N, N))
+    rc = _lib().oracle_fill_groups_amr(_p(fine), _p(layout), n, ng0, alpha.shape[0], _p(c0), _p(c1), c0.shape[1],
+                                       _p(alpha), g, _p(out))
+    if rc != 0:
+        raise ValueError("bad AMR layout or sizes")
     return out
 
 

@@ -968,6 +968,85 @@ int oracle_fill_groups_interp(const double* coarse, int cn, const int* layout, i
   return 0;
 }
 
+// AMR preparation step for groups next to coarse-fine boundaries (Sec. 4.2:
+// ghost data by spatial and temporal interpolation).  Group G of level l =
+// layout[G][0] covers interior cells layout[G][1..3] + [0, 16) of the level
+// grid, which spans the periodic unit box with nl = 16 * (ng0 << l) cells per
+// side.  Each cell of its padded region [5][N][N][N] (N = 16 + 2g) is
+//  * an interior cell: the group's own value from fine[G];
+//  * a ghost cell covered by another group of the same level: that group's
+//    value (where several groups cover it, the highest index);
+//  * any other ghost cell: the coarse state at the fine sub-step time,
+//    (1 - alpha_l) * coarse0 + alpha_l * coarse1 at the coarse cell centres,
+//    interpolated trilinearly to the fine cell centre (as
+//    oracle_fill_groups_interp, with base_dh = 1 / (16 ng0)).
+// fine: [n][5][16][16][16]; coarse0/1: [5][cn][cn][cn]; alpha: [n_levels].
+int oracle_fill_groups_amr(const double* fine, const int* layout, int n_groups, int ng0, int n_levels,
+                           const double* coarse0, const double* coarse1, int cn, const double* alpha, int g,
+                           double* groups) {
+  if (ng0 <= 0 || n_levels <= 0 || cn <= 0 || g < 0) return -1;
+  const int N = 16 + 2 * g;
+  const long gc = (long)N * N * N, cc = (long)cn * cn * cn;
+  for (int G = 0; G < n_groups; ++G) {
+    const int* L = layout + 4 * G;
+    const int lev = L[0];
+    if (lev < 0 || lev >= n_levels) return -1;
+    const int nl = 16 * (ng0 << lev);
+    const double dh = 1.0 / (double)nl;
+    for (int k = 0; k < N; ++k)
+      for (int j = 0; j < N; ++j)
+        for (int i = 0; i < N; ++i) {
+          double* o = groups + (long)G * 5 * gc + ((long)k * N + j) * N + i;
+          const int ci = i - g, cj = j - g, ck = k - g;
+          if (ci >= 0 && ci < 16 && cj >= 0 && cj < 16 && ck >= 0 && ck < 16) {
+            for (int n = 0; n < 5; ++n) o[n * gc] = fine[((long)G * 5 + n) * 4096 + (ck * 16 + cj) * 16 + ci];
+            continue;
+          }
+          // Level-grid cell (periodic) and the same-level group covering it.
+          const int p[3] = {((L[1] + ci) % nl + nl) % nl, ((L[2] + cj) % nl + nl) % nl, ((L[3] + ck) % nl + nl) % nl};
+          int owner = -1;
+          for (int H = 0; H < n_groups; ++H) {
+            const int* M = layout + 4 * H;
+            if (M[0] != lev) continue;
+            bool in = true;
+            for (int a = 0; a < 3; ++a) in = in && p[a] >= M[1 + a] && p[a] < M[1 + a] + 16;
+            if (in) owner = H;  // highest index wins
+          }
+          if (owner >= 0) {
+            const int* M = layout + 4 * owner;
+            const long c = ((long)(p[2] - M[3]) * 16 + (p[1] - M[2])) * 16 + (p[0] - M[1]);
+            for (int n = 0; n < 5; ++n) o[n * gc] = fine[((long)owner * 5 + n) * 4096 + c];
+            continue;
+          }
+          const double pos[3] = {((double)(L[1] + ci) + 0.5) * dh * cn - 0.5, ((double)(L[2] + cj) + 0.5) * dh * cn - 0.5,
+                                 ((double)(L[3] + ck) + 0.5) * dh * cn - 0.5};
+          int lo[3], hi[3];
+          double w[3];
+          for (int a = 0; a < 3; ++a) {
+            const double f = std::floor(pos[a]);
+            w[a] = pos[a] - f;
+            const int l = (int)f;
+            lo[a] = ((l % cn) + cn) % cn;
+            hi[a] = (lo[a] + 1) % cn;
+          }
+          const double al = alpha[lev];
+          for (int n = 0; n < 5; ++n) {
+            double v = 0.0;
+            for (int dz = 0; dz < 2; ++dz)
+              for (int dy = 0; dy < 2; ++dy)
+                for (int dx = 0; dx < 2; ++dx) {
+                  const double wt = (dx ? w[0] : 1.0 - w[0]) * (dy ? w[1] : 1.0 - w[1]) * (dz ? w[2] : 1.0 - w[2]);
+                  const long q = n * cc + ((long)(dz ? hi[2] : lo[2]) * cn + (dy ? hi[1] : lo[1])) * cn +
+                                 (dx ? hi[0] : lo[0]);
+                  v += wt * ((1.0 - al) * coarse0[q] + al * coarse1[q]);
+                }
+            o[n * gc] = v;
+          }
+        }
+  }
+  return 0;
+}
+
 // CFL time step from conserved cells (any layout; n_cells cells per
 // variable-plane, n_blocks blocks of [5][n_cells]):
 //   dt = cfl * dh / max over cells of max_d(|v_d| + c).

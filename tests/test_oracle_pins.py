@@ -584,3 +584,112 @@ def test_periodic_ghost_fill_wraps(oracle):
     np.testing.assert_array_equal(G[0, :, 2:18, 2:18, 0:2], box[:, :, :, 30:32])  # x wraps to the far end
     np.testing.assert_array_equal(G[1, :, 2:18, 2:18, 0:2], box[:, :, :, 14:16])
     np.testing.assert_array_equal(G[0, :, 0, 2:18, 2:18], box[:, 14, :, :16])  # z wraps (nz = 16)
+
+
+# ---- AMR preparation step (Sec. 4.2): interiors, same-level neighbours,
+#      spatial and temporal interpolation of the coarse state --------------
+
+def _amr_gather(fine, layout, ng0, lev, g, G):
+    """Brute force: the padded region of group G read from the level's
+    groups by periodic position, with a coverage mask (numpy indexing)."""
+    N = 16 + 2 * g
+    nl = 16 * (ng0 << lev)
+    owner = -np.ones((nl, nl, nl), dtype=np.int64)
+    for H, (lv, ox, oy, oz) in enumerate(layout):
+        if lv == lev:
+            owner[oz:oz + 16, oy:oy + 16, ox:ox + 16] = H
+    ox, oy, oz = layout[G][1:]
+    idx = [(np.arange(N) - g + o) % nl for o in (ox, oy, oz)]
+    Z, Y, X = np.meshgrid(idx[2], idx[1], idx[0], indexing="ij")
+    own = owner[Z, Y, X]
+    vals = np.zeros((5, N, N, N))
+    m = own >= 0
+    sel = own[m]
+    oxs, oys, ozs = (layout[sel, 1], layout[sel, 2], layout[sel, 3])
+    for n in range(5):
+        vals[n][m] = fine[sel, n, Z[m] - ozs, Y[m] - oys, X[m] - oxs]
+    return vals, m
+
+
+def test_amr_fill_linear_coarse_field_is_exact(oracle):
+    """A coarse state linear in space and in time is reproduced exactly
+    (trilinear interpolation and the linear time blend are exact for it)
+    at every ghost cell of isolated groups away from the periodic wrap;
+    interiors are the groups' own values."""
+    rng = np.random.default_rng(11)
+    cn, ng0 = 16, 4
+    layout = np.array([[0, 16, 16, 16], [1, 48, 48, 48]], dtype=np.int32)
+    alpha = [0.25, 0.75]
+    ax = np.arange(cn, dtype=np.float64)
+    Z, Y, X = np.meshgrid(ax, ax, ax, indexing="ij")
+    a0, b0 = rng.normal(size=5), rng.normal(size=(5, 3))
+    a1, b1 = rng.normal(size=5), rng.normal(size=(5, 3))
+    c0 = np.stack([a0[n] + b0[n, 0] * X + b0[n, 1] * Y + b0[n, 2] * Z for n in range(5)])
+    c1 = np.stack([a1[n] + b1[n, 0] * X + b1[n, 1] * Y + b1[n, 2] * Z for n in range(5)])
+    fine = rng.normal(size=(2, 5, 16, 16, 16))
+    g = 2
+    N = 16 + 2 * g
+    got = oracle.fill_groups_amr(fine, layout, ng0, alpha, c0, c1, g)
+    for G, (lev, ox, oy, oz) in enumerate(layout):
+        dh = 1.0 / (16 * (ng0 << lev))
+        p = [((o + np.arange(N) - g) + 0.5) * dh * cn - 0.5 for o in (ox, oy, oz)]
+        assert min(q.min() for q in p) > 0 and max(q.max() for q in p) < cn - 1  # no coarse wrap
+        PZ, PY, PX = np.meshgrid(p[2], p[1], p[0], indexing="ij")
+        al = alpha[lev]
+        want = np.stack([(1 - al) * (a0[n] + b0[n, 0] * PX + b0[n, 1] * PY + b0[n, 2] * PZ)
+                         + al * (a1[n] + b1[n, 0] * PX + b1[n, 1] * PY + b1[n, 2] * PZ) for n in range(5)])
+        want[:, g:g + 16, g:g + 16, g:g + 16] = fine[G]
+        np.testing.assert_allclose(got[G], want, rtol=0, atol=1e-12 * np.abs(want).max())
+        np.testing.assert_array_equal(got[G][:, g:g + 16, g:g + 16, g:g + 16], fine[G])
+
+
+def test_amr_fill_fully_covered_level_is_a_periodic_gather(oracle):
+    """Every ghost cell of a fully covered level comes from a neighbour: the
+    result is the periodic gather of the level's box, and the coarse state
+    (NaN here) is never read."""
+    rng = np.random.default_rng(12)
+    ng0 = 2
+    pos = [(x, y, z) for z in range(2) for y in range(2) for x in range(2)]
+    layout = np.array([[0, 16 * x, 16 * y, 16 * z] for (x, y, z) in pos], dtype=np.int32)
+    fine = rng.normal(size=(8, 5, 16, 16, 16))
+    nan = np.full((5, 4, 4, 4), np.nan)
+    for g in (2, 3):
+        got = oracle.fill_groups_amr(fine, layout, ng0, [0.5], nan, nan, g)
+        box = W.groups_to_box(fine, 32, 32, 32)
+        want = oracle.fill_ghosts_periodic(box, g)
+        np.testing.assert_array_equal(got, want)
+        for G in range(8):
+            vals, m = _amr_gather(fine, layout, ng0, 0, g, G)
+            assert m.all()
+            np.testing.assert_array_equal(got[G], vals)
+
+
+def test_amr_fill_mixed_coverage_and_time_limits(oracle):
+    """Sparse groups on two levels: ghost cells covered by a same-level group
+    (found by brute force) copy it bit for bit; the others equal the plain
+    trilinear interpolation of the time-blended coarse state; alpha = 0 and
+    alpha = 1 give the interpolation of coarse0 and coarse1 bit for bit."""
+    rng = np.random.default_rng(13)
+    ng0, cn, g = 1, 8, 3
+    layout = np.array([[0, 0, 0, 0], [1, 0, 0, 0], [1, 16, 0, 0], [1, 16, 16, 16], [1, 0, 16, 0]], dtype=np.int32)
+    fine = rng.normal(size=(5, 5, 16, 16, 16))
+    c0 = rng.normal(size=(5, cn, cn, cn))
+    c1 = rng.normal(size=(5, cn, cn, cn))
+    for alpha, blend in (([0.0, 0.0], c0), ([1.0, 1.0], c1), ([0.3, 0.6], None)):
+        got = oracle.fill_groups_amr(fine, layout, ng0, alpha, c0, c1, g)
+        for G, (lev, *_rest) in enumerate(layout):
+            vals, m = _amr_gather(fine, layout, ng0, lev, g, G)
+            for n in range(5):
+                np.testing.assert_array_equal(got[G, n][m], vals[n][m])
+            b = blend if blend is not None else (1 - alpha[lev]) * c0 + alpha[lev] * c1
+            interp = oracle.fill_groups_interp(b, layout[G:G + 1], g, 1.0 / 16)[0]
+            if blend is not None:
+                for n in range(5):
+                    np.testing.assert_array_equal(got[G, n][~m], interp[n][~m])
+            elif (~m).any():
+                err = np.abs(got[G][:, ~m] - interp[:, ~m]).max()
+                assert err <= 1e-15 * np.abs(interp).max()
+            if lev == 0:
+                assert m.all()  # one group fills level 0: its ghosts wrap onto itself
+            else:
+                assert (~m).any() and m.sum() > 4096  # both kinds of ghost cells occur
