@@ -150,6 +150,55 @@ int hydro_fill_ghosts_periodic(const void* box, int nx, int ny, int nz, int g, i
 int hydro_fill_groups_interp(const void* coarse, int cn, const int* layout, int n_groups, int g, double base_dh,
                              int flags, void* groups_out, void* stream);
 
+/*
+ * AMR levels for the preparation step of groups next to coarse-fine
+ * boundaries (Sec. 4.2).  Level l (0 <= l < n_levels <= HYDRO_MAX_LEVELS)
+ * spans the periodic unit box with ng_l = ng0 << l groups, i.e. 16 ng_l
+ * cells, per side.  A group's layout entry (level, ox, oy, oz) gives its
+ * first interior cell on its level grid; the origins are multiples of 16
+ * in [0, 16 ng_l).
+ *
+ * The group map (device int32, hydro_group_map_len(ng0, n_levels) entries)
+ * holds, level after level, the index of the group at each group position
+ * or -1: map[off_l + (gz ng_l + gy) ng_l + gx] with off_l = sum over m < l of
+ * ng_m^3.  hydro_group_map_len returns that length, or -1 for ng0 <= 0, a
+ * level count outside [1, HYDRO_MAX_LEVELS] or 2^31 entries or more.
+ */
+#define HYDRO_MAX_LEVELS 8
+long long hydro_group_map_len(int ng0, int n_levels);
+
+/*
+ * Builds the group map from layout (device int32 [n_groups][4]) into map_out
+ * (device, caller-owned, hydro_group_map_len entries).  Entries whose level is
+ * out of range or whose origin is off the level's 16-cell grid are left out;
+ * where two groups share a position the higher index is kept.
+ * Errors: HYDRO_EINVAL (bad ng0 / n_levels / n_groups, null pointer).
+ */
+int hydro_build_group_map(const int* layout, int n_groups, int ng0, int n_levels, int* map_out, void* stream);
+
+/*
+ * Preparation step (Sec. 4.2) with spatial and temporal interpolation:
+ * builds each group's padded input [n_groups][5][N][N][N] (N = 16 + 2g,
+ * 0 <= g <= 4) from
+ *  - its own interior, fine[group][5][16][16][16] (the level's state at the
+ *    fine time);
+ *  - for a ghost cell that a group of the same level covers (by the map,
+ *    periodic on the level grid): that group's value;
+ *  - for every other ghost cell: the coarse state at the fine time,
+ *    (1 - alpha[l]) coarse0 + alpha[l] coarse1 (both [5][cn][cn][cn],
+ *    periodic on the unit box, at the start and the end of the coarse
+ *    step), interpolated trilinearly to the cell centre.
+ * alpha is a HOST array of n_levels weights in [0, 1].  Copies are exact;
+ * interpolated values are formed in FP64 and rounded to the buffer type.
+ * The map must be the one built for this layout (hydro_build_group_map);
+ * entries naming no group of the call count as empty.  flags: HYDRO_F64 or 0.
+ * Errors: HYDRO_EINVAL (sizes, g, alpha, flags, null pointers),
+ * HYDRO_EALIAS (groups_out overlaps fine or a coarse state), HYDRO_EHIP.
+ */
+int hydro_fill_groups_amr(const void* fine, const int* layout, int n_groups, const int* map, int ng0, int n_levels,
+                          const void* coarse0, const void* coarse1, int cn, const double* alpha, int g, int flags,
+                          void* groups_out, void* stream);
+
 /* One segment of a batched launch: `count` groups advanced by
  * dt = (*dt) * dt_scale with cell size dh.  `dt` points to a device double,
  * so the time step can be produced on the device (e.g. by hydro_cfl_dt) and

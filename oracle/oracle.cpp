@@ -992,6 +992,8 @@ int oracle_fill_groups_amr(const double* fine, const int* layout, int n_groups, 
     const int lev = L[0];
     if (lev < 0 || lev >= n_levels) return -1;
     const int nl = 16 * (ng0 << lev);
+    for (int a = 1; a <= 3; ++a)
+      if (L[a] < 0 || L[a] >= nl || L[a] % 16) return -1;  // group origins on the level's 16-cell grid
     const double dh = 1.0 / (double)nl;
     for (int k = 0; k < N; ++k)
       for (int j = 0; j < N; ++j)

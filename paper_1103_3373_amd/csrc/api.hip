@@ -524,6 +524,63 @@ int hydro_fill_groups_interp(const void* coarse, int cn, const int* layout, int 
   return 0;
 }
 
+long long hydro_group_map_len(int ng0, int n_levels) {
+  if (ng0 <= 0 || n_levels < 1 || n_levels > HYDRO_MAX_LEVELS) return -1;
+  long long len = 0;
+  for (int l = 0; l < n_levels; ++l) {
+    const long long q = (long long)ng0 << l;
+    if (q > (1LL << 20)) return -1;
+    len += q * q * q;
+    if (len >= (1LL << 31)) return -1;
+  }
+  return len;
+}
+
+int hydro_build_group_map(const int* layout, int n_groups, int ng0, int n_levels, int* map_out, void* stream) {
+  g_err[0] = 0;
+  const long long len = hydro_group_map_len(ng0, n_levels);
+  if (len < 0) return fail(HYDRO_EINVAL, "ng0 > 0 and 1 <= n_levels <= %d with fewer than 2^31 map entries",
+                           HYDRO_MAX_LEVELS);
+  if (n_groups < 0) return fail(HYDRO_EINVAL, "n_groups < 0");
+  if (!map_out || (n_groups > 0 && !layout)) return fail(HYDRO_EINVAL, "null pointer");
+  hipError_t e = hy::launch_group_map(layout, n_groups, ng0, n_levels, len, map_out, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "group map");
+  return 0;
+}
+
+int hydro_fill_groups_amr(const void* fine, const int* layout, int n_groups, const int* map, int ng0, int n_levels,
+                          const void* coarse0, const void* coarse1, int cn, const double* alpha, int g, int flags,
+                          void* groups_out, void* stream) {
+  g_err[0] = 0;
+  if (n_groups < 0) return fail(HYDRO_EINVAL, "n_groups < 0");
+  if (hydro_group_map_len(ng0, n_levels) < 0)
+    return fail(HYDRO_EINVAL, "ng0 > 0 and 1 <= n_levels <= %d with fewer than 2^31 map entries", HYDRO_MAX_LEVELS);
+  if (g < 0 || g > 4) return fail(HYDRO_EINVAL, "ghost width must be 0..4");
+  if (cn <= 0 || cn > 4096) return fail(HYDRO_EINVAL, "coarse size out of range");
+  if (flags & ~HYDRO_F64) return fail(HYDRO_EINVAL, "only HYDRO_F64 is accepted");
+  if (!alpha) return fail(HYDRO_EINVAL, "null alpha");
+  for (int l = 0; l < n_levels; ++l)
+    if (!(alpha[l] >= 0.0 && alpha[l] <= 1.0)) return fail(HYDRO_EINVAL, "alpha[%d] outside [0, 1]", l);
+  if (n_groups == 0) return 0;
+  if (!fine || !layout || !map || !coarse0 || !coarse1 || !groups_out) return fail(HYDRO_EINVAL, "null pointer");
+  const size_t esz = (flags & HYDRO_F64) ? 8 : 4;
+  const size_t N = 16 + 2 * g;
+  const size_t ob = (size_t)n_groups * 5 * N * N * N * esz, fb = (size_t)n_groups * 5 * 4096 * esz;
+  const size_t cb = (size_t)5 * cn * cn * cn * esz;
+  if (overlap(groups_out, ob, fine, fb) || overlap(groups_out, ob, coarse0, cb) || overlap(groups_out, ob, coarse1, cb))
+    return fail(HYDRO_EALIAS, "groups_out overlaps an input");
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = (flags & HYDRO_F64)
+                     ? hy::launch_fill_amr((const double*)fine, layout, n_groups, map, ng0, n_levels,
+                                           (const double*)coarse0, (const double*)coarse1, cn, alpha, g,
+                                           (double*)groups_out, st)
+                     : hy::launch_fill_amr((const float*)fine, layout, n_groups, map, ng0, n_levels,
+                                           (const float*)coarse0, (const float*)coarse1, cn, alpha, g,
+                                           (float*)groups_out, st);
+  if (e != hipSuccess) return hip_fail(e, "AMR preparation");
+  return 0;
+}
+
 int hydro_get_diag(struct hydro_diag* out, int reset, void* stream) {
   g_err[0] = 0;
   if (!out) return fail(HYDRO_EINVAL, "null output");

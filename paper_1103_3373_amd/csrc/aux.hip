@@ -217,6 +217,186 @@ static hipError_t launch_interp_groups(const T* coarse, int cn, const int* layou
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// AMR preparation step for groups next to coarse-fine boundaries (Sec. 4.2:
+// ghost data by spatial and temporal interpolation).  Level l spans the
+// periodic unit box with ng_l = ng0 << l groups (16 ng_l cells) per side;
+// the group map holds, per level, the index of the group at each group
+// position or -1: map[off_l + (gz ng_l + gy) ng_l + gx], off_l = sum over
+// m < l of ng_m^3.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) fill_int_kernel(int* __restrict__ p, long long n, int v) {
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x)
+    p[t] = v;
+}
+// Group origins off the level's 16-cell grid or outside it, and levels out of
+// range, are left out; where two groups share a position the higher index
+// wins (atomicMax), so the map does not depend on scheduling.
+__global__ void __launch_bounds__(256) group_map_kernel(const int4* __restrict__ layout, int n_groups, int ng0,
+                                                        int n_levels, int* __restrict__ map) {
+  const int G = blockIdx.x * blockDim.x + threadIdx.x;
+  if (G >= n_groups) return;
+  const int4 L = layout[G];
+  if (L.x < 0 || L.x >= n_levels) return;
+  const long long ng = (long long)ng0 << L.x, nl = 16 * ng;
+  if (L.y < 0 || L.z < 0 || L.w < 0 || L.y >= nl || L.z >= nl || L.w >= nl || ((L.y | L.z | L.w) & 15)) return;
+  long long off = 0;
+  for (int m = 0; m < L.x; ++m) {
+    const long long q = (long long)ng0 << m;
+    off += q * q * q;
+  }
+  atomicMax(&map[off + ((long long)(L.w >> 4) * ng + (L.z >> 4)) * ng + (L.y >> 4)], G);
+}
+
+hipError_t launch_group_map(const int* layout, int n_groups, int ng0, int n_levels, long long map_len, int* map,
+                            hipStream_t st) {
+  long long blocks = (map_len + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  fill_int_kernel<<<dim3((unsigned)blocks), dim3(256), 0, st>>>(map, map_len, -1);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || n_groups == 0) return e;
+  group_map_kernel<<<dim3((unsigned)((n_groups + 255) / 256)), dim3(256), 0, st>>>((const int4*)layout, n_groups, ng0,
+                                                                                  n_levels, map);
+  return hipGetLastError();
+}
+
+// One workgroup per group, one thread per (x, y) column of its padded
+// region, marching along z.  A cell is the group's own interior value, else
+// the value of the same-level group that the map places at its (periodic)
+// position, else the coarse state blended in time, (1 - alpha_l) coarse0 +
+// alpha_l coarse1 at the four coarse points of a layer, interpolated in x
+// and y and then in z between the two layers that bracket the cell; a
+// thread keeps both layers' values and recomputes them only when the pair
+// moves.  No contraction: a plain FP64 evaluation of that expression.  Map
+// entries outside [0, n_groups) count as empty, and levels are clamped into
+// range, so every access stays inside the arrays whatever the layout holds.
+template <typename T>
+struct AmrArgs {
+  const T* fine;       // [n][5][16][16][16]
+  const int4* layout;  // [n] (level, ox, oy, oz)
+  const int* map;
+  const T* c0;         // [5][cn][cn][cn]
+  const T* c1;
+  T* out;              // [n][5][N][N][N]
+  int n_groups, ng0, n_levels, cn;
+  double alpha[8];
+};
+
+template <typename T, int G>
+__global__ void __launch_bounds__(interp_threads<G>()) fill_amr_group_kernel(AmrArgs<T> a) {
+#pragma clang fp contract(off)
+  constexpr int N = 16 + 2 * G;
+  constexpr long long nc = (long long)N * N * N;
+  const int cn = a.cn;
+  const long long cc = (long long)cn * cn * cn;
+  const long long grp = blockIdx.x;
+  const int4 L = a.layout[grp];
+  const int r = threadIdx.x;
+  if (r >= N * N) return;  // no barrier below
+  const int lev = L.x < 0 ? 0 : (L.x >= a.n_levels ? a.n_levels - 1 : L.x);
+  const long long ng = (long long)a.ng0 << lev;
+  const int nl = (int)(16 * ng);
+  long long moff = 0;
+  for (int m = 0; m < lev; ++m) {
+    const long long q = (long long)a.ng0 << m;
+    moff += q * q * q;
+  }
+  const double dh = 1.0 / (double)nl;
+  const double al = a.alpha[lev];
+  const int ci = r % N - G, cj = r / N - G;
+  const bool in_xy = ci >= 0 && ci < 16 && cj >= 0 && cj < 16;
+  const int px = wrap_index((long long)L.y + ci, nl), py = wrap_index((long long)L.z + cj, nl);
+  const double X = (((double)L.y + ci) + 0.5) * dh * cn - 0.5;
+  const double Y = (((double)L.z + cj) + 0.5) * dh * cn - 0.5;
+  const double fx0 = floor(X), fy0 = floor(Y);
+  const double ax = X - fx0, ay = Y - fy0;
+  const int x0 = wrap_index((long long)fx0, cn), y0 = wrap_index((long long)fy0, cn);
+  const int x1 = x0 + 1 == cn ? 0 : x0 + 1, y1 = y0 + 1 == cn ? 0 : y0 + 1;
+  auto layer = [&](int z, int n) -> double {
+    const long long base = (long long)n * cc + (long long)z * cn * cn;
+    const T* f0 = a.c0 + base;
+    const T* f1 = a.c1 + base;
+    auto b = [&](int q) -> double { return (1.0 - al) * (double)f0[q] + al * (double)f1[q]; };
+    const double v00 = (1.0 - ax) * b(y0 * cn + x0) + ax * b(y0 * cn + x1);
+    const double v01 = (1.0 - ax) * b(y1 * cn + x0) + ax * b(y1 * cn + x1);
+    return (1.0 - ay) * v00 + ay * v01;
+  };
+  const T* own = a.fine + grp * 5 * 4096;
+  T* o = a.out + grp * 5 * nc + r;
+  double v0[5], v1[5];
+  int zc = -1;
+  for (int k = 0; k < N; ++k) {
+    const int ck = k - G;
+    T val[5];
+    if (in_xy && ck >= 0 && ck < 16) {
+#pragma unroll
+      for (int n = 0; n < 5; ++n) val[n] = own[n * 4096 + (ck * 16 + cj) * 16 + ci];
+    } else {
+      const int pz = wrap_index((long long)L.w + ck, nl);
+      const int owner = a.map[moff + ((long long)(pz >> 4) * ng + (py >> 4)) * ng + (px >> 4)];
+      if (owner >= 0 && owner < a.n_groups) {
+        const T* s = a.fine + (long long)owner * 5 * 4096 + ((pz & 15) * 16 + (py & 15)) * 16 + (px & 15);
+#pragma unroll
+        for (int n = 0; n < 5; ++n) val[n] = s[n * 4096];
+      } else {
+        const double Z = (((double)L.w + ck) + 0.5) * dh * cn - 0.5;
+        const double fz0 = floor(Z);
+        const double az = Z - fz0;
+        const int z0 = wrap_index((long long)fz0, cn), z1 = z0 + 1 == cn ? 0 : z0 + 1;
+        if (z0 != zc) {
+          const bool shift = zc >= 0 && z0 == (zc + 1 == cn ? 0 : zc + 1);
+#pragma unroll
+          for (int n = 0; n < 5; ++n) {
+            v0[n] = shift ? v1[n] : layer(z0, n);
+            v1[n] = layer(z1, n);
+          }
+          zc = z0;
+        }
+#pragma unroll
+        for (int n = 0; n < 5; ++n) val[n] = (T)((1.0 - az) * v0[n] + az * v1[n]);
+      }
+    }
+#pragma unroll
+    for (int n = 0; n < 5; ++n) o[n * nc + (long long)k * N * N] = val[n];
+  }
+}
+
+template <typename T, int G>
+static hipError_t launch_amr_g(const AmrArgs<T>& a, hipStream_t st) {
+  fill_amr_group_kernel<T, G><<<dim3((unsigned)a.n_groups), dim3(interp_threads<G>()), 0, st>>>(a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fill_amr(const T* fine, const int* layout, int n_groups, const int* map, int ng0, int n_levels,
+                           const T* c0, const T* c1, int cn, const double* alpha, int g, T* out, hipStream_t st) {
+  if (n_groups == 0) return hipSuccess;
+  AmrArgs<T> a;
+  a.fine = fine;
+  a.layout = (const int4*)layout;
+  a.map = map;
+  a.c0 = c0;
+  a.c1 = c1;
+  a.out = out;
+  a.n_groups = n_groups;
+  a.ng0 = ng0;
+  a.n_levels = n_levels;
+  a.cn = cn;
+  for (int l = 0; l < 8; ++l) a.alpha[l] = l < n_levels ? alpha[l] : 0.0;
+  switch (g) {
+    case 0: return launch_amr_g<T, 0>(a, st);
+    case 1: return launch_amr_g<T, 1>(a, st);
+    case 2: return launch_amr_g<T, 2>(a, st);
+    case 3: return launch_amr_g<T, 3>(a, st);
+    case 4: return launch_amr_g<T, 4>(a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+template hipError_t launch_fill_amr<float>(const float*, const int*, int, const int*, int, int, const float*,
+                                           const float*, int, const double*, int, float*, hipStream_t);
+template hipError_t launch_fill_amr<double>(const double*, const int*, int, const int*, int, int, const double*,
+                                            const double*, int, const double*, int, double*, hipStream_t);
+
 template <typename T>
 hipError_t launch_fill_interp(const T* coarse, int cn, const int* layout, long long n_groups, int g, double base_dh,
                               T* out, hipStream_t st) {

@@ -95,6 +95,11 @@ int fused_block_threads();
 // Auxiliary kernels.
 template <typename T>
 hipError_t launch_fill_periodic(const T* box, int nx, int ny, int nz, int g, int grouped, T* out, hipStream_t st);
+hipError_t launch_group_map(const int* layout, int n_groups, int ng0, int n_levels, long long map_len, int* map,
+                            hipStream_t st);
+template <typename T>
+hipError_t launch_fill_amr(const T* fine, const int* layout, int n_groups, const int* map, int ng0, int n_levels,
+                           const T* c0, const T* c1, int cn, const double* alpha, int g, T* out, hipStream_t st);
 template <typename T>
 hipError_t launch_fill_interp(const T* coarse, int cn, const int* layout, long long n_groups, int g, double base_dh,
                               T* out, hipStream_t st);

@@ -23,7 +23,8 @@ F64, CHAR, FLUX_MID, PLAIN, ROE_FB_HLLC, BOX_GROUPED, BOX_SEGS = 0x01, 0x02, 0x0
 
 EXPORTS = (
     "hydro_ghost_width", "hydro_solve_groups", "hydro_cfl_dt", "hydro_conserved_sums", "hydro_cfl_dt_sums",
-    "hydro_fill_ghosts_periodic", "hydro_fill_groups_interp", "hydro_solve_batch", "hydro_autotune",
+    "hydro_fill_ghosts_periodic", "hydro_fill_groups_interp", "hydro_group_map_len", "hydro_build_group_map",
+    "hydro_fill_groups_amr", "hydro_solve_batch", "hydro_autotune",
     "hydro_set_launch_shape", "hydro_step_box", "hydro_cfl_dt_batch",
     "hydro_get_diag", "hydro_last_error", "hydro_shutdown",
 )
@@ -77,6 +78,12 @@ def lib() -> ctypes.CDLL:
     L.hydro_fill_ghosts_periodic.restype = i
     L.hydro_fill_groups_interp.argtypes = [P, i, P, i, i, d, i, P, P]
     L.hydro_fill_groups_interp.restype = i
+    L.hydro_group_map_len.argtypes = [i, i]
+    L.hydro_group_map_len.restype = ll
+    L.hydro_build_group_map.argtypes = [P, i, i, i, P, P]
+    L.hydro_build_group_map.restype = i
+    L.hydro_fill_groups_amr.argtypes = [P, P, i, P, i, i, P, P, i, ctypes.POINTER(d), i, i, P, P]
+    L.hydro_fill_groups_amr.restype = i
     L.hydro_step_box.argtypes = [P, P, P, i, i, i, P, d, d, d, i, i, i, i, i, P]
     L.hydro_step_box.restype = i
     L.hydro_cfl_dt_batch.argtypes = [P, i, ll, d, d, i, P]
@@ -219,6 +226,52 @@ def fill_groups_interp(coarse, layout, g, base_dh, out=None, stream=None):
     _check("hydro_fill_groups_interp", lib().hydro_fill_groups_interp(
         _ptr(coarse), coarse.shape[1], _ptr(layout), n, g, float(base_dh), _dtype_flag(coarse), _ptr(out),
         _stream(stream)))
+    return out
+
+
+def group_map_len(ng0, n_levels) -> int:
+    n = lib().hydro_group_map_len(int(ng0), int(n_levels))
+    if n < 0:
+        raise ValueError(f"bad AMR level sizes ng0={ng0}, n_levels={n_levels}")
+    return n
+
+
+def build_group_map(layout, ng0, n_levels, out=None, stream=None):
+    """Per-level map from group position to group index (-1 where none);
+    layout int32 [n,4] = (level, ox, oy, oz) on the device."""
+    _require(layout, "layout", dtype=torch.int32)
+    m = group_map_len(ng0, n_levels)
+    if out is None:
+        out = torch.empty((m,), dtype=torch.int32, device=layout.device)
+    _require(out, "map", shape=(m,), dtype=torch.int32)
+    _check("hydro_build_group_map", lib().hydro_build_group_map(
+        _ptr(layout), layout.shape[0], int(ng0), int(n_levels), _ptr(out), _stream(stream)))
+    return out
+
+
+def fill_groups_amr(fine, layout, gmap, ng0, alpha, coarse0, coarse1, g, out=None, stream=None):
+    """Preparation step with spatial and temporal interpolation: padded groups
+    [n,5,N,N,N] from the groups' interiors fine [n,5,16,16,16], same-level
+    neighbours (gmap from build_group_map) and the coarse pair blended at
+    alpha[level] (a host sequence, one weight per level)."""
+    _require(fine, "fine")
+    _require(layout, "layout", dtype=torch.int32)
+    _require(gmap, "map", dtype=torch.int32)
+    _require(coarse0, "coarse0", dtype=fine.dtype)
+    _require(coarse1, "coarse1", shape=coarse0.shape, dtype=fine.dtype)
+    n = layout.shape[0]
+    if tuple(fine.shape) != (n, 5, 16, 16, 16):
+        raise ValueError(f"fine has shape {tuple(fine.shape)}, expected {(n, 5, 16, 16, 16)}")
+    if gmap.shape[0] != group_map_len(ng0, len(alpha)):
+        raise ValueError("map length does not match ng0 and the level count")
+    N = 16 + 2 * g
+    if out is None:
+        out = torch.empty((n, 5, N, N, N), dtype=fine.dtype, device=fine.device)
+    _require(out, "out", shape=(n, 5, N, N, N), dtype=fine.dtype)
+    al = (ctypes.c_double * len(alpha))(*[float(x) for x in alpha])
+    _check("hydro_fill_groups_amr", lib().hydro_fill_groups_amr(
+        _ptr(fine), _ptr(layout), n, _ptr(gmap), int(ng0), len(alpha), _ptr(coarse0), _ptr(coarse1),
+        coarse0.shape[1], al, g, _dtype_flag(fine), _ptr(out), _stream(stream)))
     return out
 
 

@@ -109,3 +109,38 @@ def test_cfl_dt_sums_validation(L):
     assert L.hydro_cfl_dt_sums(P(0x1000), 4, 1.0, 1.0, 0.5, 0, P(0x2000), P(0x3000), None) == EINVAL
     assert L.hydro_cfl_dt_sums(P(0x1000), 4, 1.0, 1.4, 0.5, 0x100, P(0x2000), P(0x3000), None) == EINVAL
     assert L.hydro_cfl_dt_sums(P(0x1000), 4, 1.0, 1.4, 0.5, 0, P(0x2000), P(0x2000 - 8), None) == EALIAS
+
+
+def test_amr_preparation_validation(L):
+    """Argument checks of the AMR group map and preparation step (host only)."""
+    EINVAL, EALIAS = -1, -4
+    P = ctypes.c_void_p
+    L.hydro_group_map_len.restype = ctypes.c_longlong
+    assert L.hydro_group_map_len(16, 3) == 16 ** 3 + 32 ** 3 + 64 ** 3
+    assert L.hydro_group_map_len(0, 1) == -1
+    assert L.hydro_group_map_len(2, 0) == -1
+    assert L.hydro_group_map_len(2, 9) == -1
+    assert L.hydro_group_map_len(1 << 11, 1) == -1  # 2^33 entries
+    assert L.hydro_build_group_map(P(0x1000), 4, 0, 1, P(0x2000), None) == EINVAL
+    assert L.hydro_build_group_map(P(0x1000), -1, 2, 1, P(0x2000), None) == EINVAL
+    assert L.hydro_build_group_map(P(0x1000), 4, 2, 1, P(0), None) == EINVAL
+    al = (ctypes.c_double * 2)(0.0, 0.5)
+    bad = (ctypes.c_double * 2)(0.0, 1.5)
+    fn = L.hydro_fill_groups_amr
+    fn.argtypes = [P, P, ctypes.c_int, P, ctypes.c_int, ctypes.c_int, P, P, ctypes.c_int,
+                   ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_int, P, P]
+    ok = dict(fine=P(0x10000000), lay=P(0x1000), m=P(0x2000), c0=P(0x20000000), c1=P(0x30000000), out=P(0x40000000))
+
+    def call(n=4, ng0=2, nl=2, cn=8, alpha=al, g=3, flags=0, **kw):
+        a = dict(ok, **kw)
+        return fn(a["fine"], a["lay"], n, a["m"], ng0, nl, a["c0"], a["c1"], cn, alpha, g, flags, a["out"], None)
+
+    assert call(n=-1) == EINVAL
+    assert call(ng0=0) == EINVAL
+    assert call(g=5) == EINVAL
+    assert call(cn=0) == EINVAL
+    assert call(alpha=bad) == EINVAL
+    assert call(flags=0x02) == EINVAL
+    assert call(fine=P(0)) == EINVAL
+    assert call(out=P(0x10000000 + 64)) == EALIAS
+    assert call(n=0) == 0

@@ -276,3 +276,88 @@ def test_full_size_sampled_groups(H):
     s0 = H.conserved_sums(_dev(W.box_to_groups(box).astype(np.float32), torch.float32), 1 / 256).cpu().numpy()
     s1 = H.conserved_sums(out, 1 / 256).cpu().numpy()
     assert abs(s1[0] - s0[0]) <= 1e-6 * s0[0] and abs(s1[4] - s0[4]) <= 1e-6 * s0[4]
+
+
+def _amr_case(ng0, counts, cn, seed):
+    rng = np.random.default_rng(seed)
+    lay = W.amr_layout(counts, base_n=16 * ng0, seed=seed)
+    n = lay.shape[0]
+    fine = W.amr_coarse_field(16, seed=seed)[None].repeat(n, 0) * (1 + 0.1 * rng.random((n, 1, 1, 1, 1)))
+    fine = np.ascontiguousarray(fine)
+    c0 = W.amr_coarse_field(cn, seed=seed + 1)
+    c1 = c0 * (1 + 0.05 * rng.standard_normal(c0.shape))
+    return lay, fine, c0, c1
+
+
+def test_group_map_matches_numpy(H):
+    """Per-level group map: -1 where no group, the group index elsewhere;
+    duplicate positions keep the higher index; an origin off the 16-cell grid
+    is left out."""
+    ng0, n_levels = 2, 3
+    lay = W.amr_layout((5, 20, 60), base_n=32, seed=21)
+    lay = np.concatenate([lay, lay[3:4], np.array([[1, 8, 0, 0]], dtype=np.int32)]).astype(np.int32)
+    want = np.full(H.group_map_len(ng0, n_levels), -1, dtype=np.int32)
+    off = 0
+    offs = []
+    for lv in range(n_levels):
+        offs.append(off)
+        off += (ng0 << lv) ** 3
+    for G, (lv, ox, oy, oz) in enumerate(lay):
+        if ox % 16 or oy % 16 or oz % 16:
+            continue
+        ng = ng0 << lv
+        q = offs[lv] + ((oz // 16) * ng + oy // 16) * ng + ox // 16
+        want[q] = max(want[q], G)
+    got = H.build_group_map(torch.from_numpy(lay).cuda(), ng0, n_levels).cpu().numpy()
+    np.testing.assert_array_equal(got, want)
+
+
+@pytest.mark.parametrize("g", [2, 3, 4])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_amr_fill_matches_oracle(H, g, dtype):
+    """Preparation with same-level neighbours and time-blended coarse ghosts
+    on three sparse levels: copied cells bit for bit, interpolated cells to
+    FP64 rounding (the oracle sums eight weighted corners, the kernel
+    interpolates axis by axis) or to FP32 rounding of the result."""
+    ng0, alpha = 2, [0.0, 0.25, 0.625]
+    lay, fine, c0, c1 = _amr_case(ng0, (4, 12, 40), 8, 31)
+    if dtype == torch.float32:
+        fine, c0, c1 = (a.astype(np.float32).astype(np.float64) for a in (fine, c0, c1))
+    want = O.fill_groups_amr(fine, lay, ng0, alpha, c0, c1, g)
+    lay_d = torch.from_numpy(lay).cuda()
+    gmap = H.build_group_map(lay_d, ng0, len(alpha))
+    got = H.fill_groups_amr(_dev(fine, dtype), lay_d, gmap, ng0, alpha, _dev(c0, dtype), _dev(c1, dtype), g)
+    got = got.cpu().numpy().astype(np.float64)
+    if dtype == torch.float64:
+        assert scaled_max_err(got, want) <= 1e-15
+    else:
+        assert scaled_max_err(got, want) <= 2e-7
+    # Interiors and neighbour copies are exact copies of the fine values.
+    N = 16 + 2 * g
+    inner = np.zeros((N, N, N), dtype=bool)
+    inner[g:g + 16, g:g + 16, g:g + 16] = True
+    np.testing.assert_array_equal(got[:, :, inner], want[:, :, inner])
+    nl = [16 * (ng0 << lv) for lv in range(3)]
+    cover = {lv: np.zeros((nl[lv],) * 3, dtype=bool) for lv in range(3)}
+    for lv, ox, oy, oz in lay:
+        cover[lv][oz:oz + 16, oy:oy + 16, ox:ox + 16] = True
+    for G, (lv, ox, oy, oz) in enumerate(lay):
+        idx = [(np.arange(N) - g + o) % nl[lv] for o in (ox, oy, oz)]
+        m = cover[lv][np.ix_(idx[2], idx[1], idx[0])]
+        np.testing.assert_array_equal(got[G][:, m], want[G][:, m])
+
+
+def test_amr_fill_full_level_is_periodic_fill(H):
+    """A fully covered level: the preparation equals the periodic ghost fill
+    of the level's box bit for bit (no coarse value is used)."""
+    rng = np.random.default_rng(41)
+    lay = np.array([[0, 16 * x, 16 * y, 16 * z] for z in range(2) for y in range(2) for x in range(2)],
+                   dtype=np.int32)
+    fine = rng.standard_normal((8, 5, 16, 16, 16))
+    box = W.groups_to_box(fine, 32, 32, 32)
+    lay_d = torch.from_numpy(lay).cuda()
+    gmap = H.build_group_map(lay_d, 2, 1)
+    c = _dev(np.full((5, 4, 4, 4), 7.0), torch.float64)
+    got = H.fill_groups_amr(_dev(fine, torch.float64), lay_d, gmap, 2, [0.5], c, c, 3).cpu().numpy()
+    want = H.fill_ghosts_periodic(_dev(box, torch.float64), 3).cpu().numpy()
+    np.testing.assert_array_equal(got, want)
