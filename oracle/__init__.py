@@ -61,6 +61,8 @@ def _lib(counting: bool = False) -> ctypes.CDLL:
     L.oracle_fill_groups_interp.restype = i
     L.oracle_fill_groups_amr.argtypes = [P, P, i, i, i, P, P, i, P, i, P]
     L.oracle_fill_groups_amr.restype = i
+    L.oracle_amr_correct.argtypes = [P, i, i, i, P, P, P, i, P, d, d]
+    L.oracle_amr_correct.restype = i
     L.oracle_cfl_dt.argtypes = [P, ctypes.c_long, ctypes.c_long, d, d, d]
     L.oracle_cfl_dt.restype = d
     L.oracle_conserved_sums.argtypes = [P, ctypes.c_long, ctypes.c_long, d, P]
@@ -177,6 +179,23 @@ def fill_groups_amr(fine, layout, ng0, alpha, coarse0, coarse1, g) -> np.ndarray
                                        _p(alpha), g, _p(out))
     if rc != 0:
         raise ValueError("bad AMR layout or sizes")
+    return out
+
+
+def amr_correct(coarse, shape, cflux, fine, flayout, fflux, dt, dh) -> np.ndarray:
+    """Coarse-grid correction after a coarse step (refluxing at coarse-fine
+    faces, then restriction of the refined patches); returns the corrected
+    copy of the coarse box [Gc][5][16]^3 (patch-group order, shape = (nx, ny,
+    nz)).  cflux [Gc][3][3][5][16][16] (with mid planes), fine [nf][5][16]^3
+    on the fine grid (ratio 2), flayout int32 [nf][4] (unused, ox, oy, oz),
+    fflux [nf][3][2][5][16][16] averaged over the fine sub-steps."""
+    out = _f64(coarse).copy()
+    cf, fi, ff = _f64(cflux), _f64(fine), _f64(fflux)
+    lay = np.ascontiguousarray(flayout, dtype=np.int32)
+    nx, ny, nz = shape
+    rc = _lib().oracle_amr_correct(_p(out), nx, ny, nz, _p(cf), _p(fi), _p(lay), lay.shape[0], _p(ff), dt, dh)
+    if rc != 0:
+        raise ValueError("fine groups must cover whole coarse patches inside the coarse box")
     return out
 
 

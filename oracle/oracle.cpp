@@ -1049,6 +1049,98 @@ int oracle_fill_groups_amr(const double* fine, const int* layout, int n_groups, 
   return 0;
 }
 
+// Coarse-grid correction (Sec. 2 step 5, Sec. 4.3): after one step of a
+// periodic coarse box and the sub-steps of refined groups of ratio 2, every
+// fine group covering exactly one coarse patch (8^3 coarse cells: fine
+// origin (ox, oy, oz) on the fine grid, multiples of 16):
+//  * refluxing: an uncovered coarse cell a whose neighbour b across a face
+//    is covered by fine group F had its update formed with the coarse flux
+//    Fc of that face; it is corrected to the mean Ff of the four fine fluxes
+//    on the same face (F's face towards a, averaged over the sub-steps by
+//    the caller): U_a -= dt/dh (Ff - Fc) if b lies on a's + side,
+//    U_a += dt/dh (Ff - Fc) if on its - side (directions x, y, z, sides -, +
+//    in that order);
+//  * restriction: a covered coarse cell becomes the mean of its 8 children.
+// coarse: [Gc][5][16][16][16] in patch-group order of an nx x ny x nz box;
+// cflux: [Gc][3][3][5][16][16] (faces -, +, mid at offset 8; transverse
+// indices (z, y), (z, x), (y, x)); fine: [nf][5][16][16][16]; flayout:
+// [nf][4] (unused, ox, oy, oz); fflux: [nf][3][2][5][16][16].
+int oracle_amr_correct(double* coarse, int nx, int ny, int nz, const double* cflux, const double* fine,
+                       const int* flayout, int nf, const double* fflux, double dt, double dh) {
+  if (nx % 16 || ny % 16 || nz % 16) return -1;
+  const int n3[3] = {nx, ny, nz};
+  const int ngx = nx / 16, ngy = ny / 16;
+  for (int F = 0; F < nf; ++F)
+    for (int a = 1; a <= 3; ++a)
+      if (flayout[4 * F + a] % 16 || flayout[4 * F + a] < 0 || flayout[4 * F + a] >= 2 * n3[a - 1]) return -1;
+  auto cell = [&](int x, int y, int z, int n) -> double& {
+    const long G = ((long)(z / 16) * ngy + y / 16) * ngx + x / 16;
+    return coarse[(G * 5 + n) * 4096 + ((z % 16) * 16 + (y % 16)) * 16 + x % 16];
+  };
+  auto owner = [&](const int c[3]) -> int {  // fine group covering coarse cell c, or -1
+    int o = -1;
+    for (int F = 0; F < nf; ++F) {
+      bool in = true;
+      for (int a = 0; a < 3; ++a) {
+        const int lo = flayout[4 * F + 1 + a] / 2;
+        in = in && c[a] >= lo && c[a] < lo + 8;
+      }
+      if (in) o = F;
+    }
+    return o;
+  };
+  // Refluxing (uncovered cells only; increments do not depend on U).
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const int c[3] = {x, y, z};
+        if (owner(c) >= 0) continue;
+        const long G = ((long)(z / 16) * ngy + y / 16) * ngx + x / 16;
+        for (int d = 0; d < 3; ++d)
+          for (int side = -1; side <= 1; side += 2) {
+            int b[3] = {x, y, z};
+            b[d] = (b[d] + side + n3[d]) % n3[d];
+            const int F = owner(b);
+            if (F < 0) continue;
+            // transverse coordinates (slow, fast) of the face: x (z, y), y (z, x), z (y, x)
+            const int ts = d == 2 ? 1 : 2, tf = d == 0 ? 1 : 0;
+            const int loc = c[d] % 16;
+            int slot;
+            if (side > 0) slot = loc == 15 ? 1 : (loc == 7 ? 2 : -1);
+            else slot = loc == 0 ? 0 : (loc == 8 ? 2 : -1);
+            if (slot < 0) return -2;  // fine coverage off the coarse patch grid
+            const int fo[3] = {flayout[4 * F + 1], flayout[4 * F + 2], flayout[4 * F + 3]};
+            const int fs0 = 2 * (c[ts] - fo[ts] / 2), ff0 = 2 * (c[tf] - fo[tf] / 2);
+            const int fslot = side > 0 ? 0 : 1;  // F's face towards a
+            for (int n = 0; n < 5; ++n) {
+              const double Fc = cflux[((((G * 3 + d) * 3 + slot) * 5 + n) * 16 + c[ts] % 16) * 16 + c[tf] % 16];
+              double Ff = 0.0;
+              for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j)
+                  Ff += fflux[((((long)(F * 3 + d) * 2 + fslot) * 5 + n) * 16 + fs0 + i) * 16 + ff0 + j];
+              Ff *= 0.25;
+              cell(x, y, z, n) += (side > 0 ? -1.0 : 1.0) * (dt / dh) * (Ff - Fc);
+            }
+          }
+      }
+  // Restriction.
+  for (int F = 0; F < nf; ++F) {
+    const int* o = flayout + 4 * F;
+    for (int k = 0; k < 8; ++k)
+      for (int j = 0; j < 8; ++j)
+        for (int i = 0; i < 8; ++i)
+          for (int n = 0; n < 5; ++n) {
+            double s = 0.0;
+            for (int dz = 0; dz < 2; ++dz)
+              for (int dy = 0; dy < 2; ++dy)
+                for (int dx = 0; dx < 2; ++dx)
+                  s += fine[((long)F * 5 + n) * 4096 + ((2 * k + dz) * 16 + 2 * j + dy) * 16 + 2 * i + dx];
+            cell(o[1] / 2 + i, o[2] / 2 + j, o[3] / 2 + k, n) = 0.125 * s;
+          }
+  }
+  return 0;
+}
+
 // CFL time step from conserved cells (any layout; n_cells cells per
 // variable-plane, n_blocks blocks of [5][n_cells]):
 //   dt = cfl * dh / max over cells of max_d(|v_d| + c).

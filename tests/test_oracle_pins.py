@@ -693,3 +693,83 @@ def test_amr_fill_mixed_coverage_and_time_limits(oracle):
                 assert m.all()  # one group fills level 0: its ghosts wrap onto itself
             else:
                 assert (~m).any() and m.sum() > 4096  # both kinds of ghost cells occur
+
+
+# ---- coarse-grid correction (Sec. 2 step 5, Sec. 4.3) ----------------------
+
+def _amr_two_level_step(oracle, reflux=True, scheme=2, recon=1, rs=1):
+    """One coarse step of a 32^3 periodic box and two fine sub-steps of two
+    adjacent refined groups (ratio 2), then the coarse-grid correction.
+    Returns (total before, total after) of the conserved variables."""
+    gamma = 1.4
+    n = 32
+    box = W.lognormal_blast_box(n, gamma=gamma, seed=17, radius_cells=3)
+    dh_c = 1.0 / n
+    lay = np.array([[0, 16, 16, 16], [0, 32, 16, 16]], dtype=np.int32)  # fine-grid origins (64^3)
+    # Fine interiors by injection: each fine cell takes its parent's value.
+    fine = np.stack([np.repeat(np.repeat(np.repeat(
+        box[:, o[3] // 2:o[3] // 2 + 8, o[2] // 2:o[2] // 2 + 8, o[1] // 2:o[1] // 2 + 8], 2, 1), 2, 2), 2, 3)
+        for o in lay])
+    total0 = box.reshape(5, -1).sum(1) * dh_c ** 3
+    g = oracle.ghost_width(scheme, recon)
+    dt = oracle.cfl_dt(box, dh_c, gamma, 0.4)
+    flags = oracle.F_CHAR | oracle.F_FLUX_MID
+    cg, cflux = oracle.solve_groups(oracle.fill_ghosts_periodic(box, g), g, dt, dh_c, gamma, scheme, recon, rs, 1,
+                                    flags, want_flux=True)
+    new_box = W.groups_to_box(cg, n, n, n)
+    fflux = np.zeros((2, 3, 2, 5, 16, 16))
+    for s in range(2):
+        pad = oracle.fill_groups_amr(fine, lay, 4, [0.5 * s], box, new_box, g)
+        fine, fl = oracle.solve_groups(pad, g, 0.5 * dt, 0.5 * dh_c, gamma, scheme, recon, rs, 1, oracle.F_CHAR,
+                                       want_flux=True)
+        fflux += 0.5 * fl
+    if not reflux:  # zero coarse and fine fluxes: no flux correction, restriction only
+        cflux, fflux = np.zeros_like(cflux), np.zeros_like(fflux)
+    out = oracle.amr_correct(cg, (n, n, n), cflux, fine, lay, fflux, dt, dh_c)
+    total1 = W.groups_to_box(out, n, n, n).reshape(5, -1).sum(1) * dh_c ** 3
+    return total0, total1, out, fine
+
+
+@pytest.mark.parametrize("scheme,recon,rs", [(2, 1, 1), (0, 0, 0), (1, 1, 2)])
+def test_coarse_grid_correction_conserves(oracle, scheme, recon, rs):
+    """A coarse step, two fine sub-steps and the correction (refluxing, then
+    restriction) conserve mass, momentum and energy of the periodic domain to
+    round-off; restriction alone does not."""
+    t0, t1, out, fine = _amr_two_level_step(oracle, True, scheme, recon, rs)
+    scale = np.abs(t0).max()
+    assert np.abs(t1 - t0).max() <= 1e-13 * scale, (t1 - t0)
+    u0, u1, _, _ = _amr_two_level_step(oracle, False, scheme, recon, rs)
+    assert np.abs(u1 - u0).max() > 1e-9 * scale
+
+
+def test_restriction_is_the_mean_of_the_children(oracle):
+    """Covered coarse cells become the mean of their 8 fine children (a
+    linear fine field restricts to its value at the coarse cell centre);
+    refluxing touches exactly the coarse cells that share a face with the
+    refined patch."""
+    rng = np.random.default_rng(5)
+    n = 32
+    coarse = rng.standard_normal((8, 5, 16, 16, 16))
+    lay = np.array([[0, 0, 16, 48]], dtype=np.int32)  # coarse patch x 0..7, y 8..15, z 24..31
+    ax = np.arange(16) + 0.5
+    Z, Y, X = np.meshgrid(ax, ax, ax, indexing="ij")
+    fine = np.stack([1.0 + n_ * 0.1 + 0.3 * X - 0.2 * Y + 0.05 * Z for n_ in range(5)])[None]
+    cflux = rng.standard_normal((8, 3, 3, 5, 16, 16))
+    fflux = np.zeros((1, 3, 2, 5, 16, 16))
+    out = oracle.amr_correct(coarse, (n, n, n), cflux, fine, lay, fflux, 1e-3, 1.0 / n)
+    box0 = W.groups_to_box(coarse, n, n, n)
+    box1 = W.groups_to_box(out, n, n, n)
+    cz, cy, cx = np.meshgrid(np.arange(8) + 0.5, np.arange(8) + 0.5, np.arange(8) + 0.5, indexing="ij")
+    for v in range(5):
+        want = 1.0 + v * 0.1 + 0.3 * (2 * cx) - 0.2 * (2 * cy) + 0.05 * (2 * cz)
+        np.testing.assert_allclose(box1[v, 24:32, 8:16, 0:8], want, rtol=0, atol=1e-14)
+    far = np.ones((n, n, n), dtype=bool)
+    far[24:32, 8:16, 0:8] = False
+    # The six slabs of coarse cells next to the refined patch (periodic) change
+    # (zero fine flux against random coarse flux); every other cell does not.
+    for sl in ((slice(23, 24), slice(8, 16), slice(0, 8)), (slice(24, 32), slice(7, 8), slice(0, 8)),
+               (slice(24, 32), slice(16, 17), slice(0, 8)), (slice(24, 32), slice(8, 16), slice(8, 9)),
+               (slice(24, 32), slice(8, 16), slice(31, 32)), (slice(0, 1), slice(8, 16), slice(0, 8))):
+        far[sl] = False
+        assert np.abs(box1[:, sl[0], sl[1], sl[2]] - box0[:, sl[0], sl[1], sl[2]]).min() > 0
+    np.testing.assert_array_equal(box1[:, far], box0[:, far])
