@@ -199,6 +199,43 @@ int hydro_fill_groups_amr(const void* fine, const int* layout, int n_groups, con
                           const void* coarse0, const void* coarse1, int cn, const double* alpha, int g, int flags,
                           void* groups_out, void* stream);
 
+/*
+ * Coarse-grid correction after one coarse step (Sec. 2 step 5: the fluxes
+ * stored on patch boundaries; Sec. 4.3: correcting the coarse-grid data),
+ * in place on coarse (the state after the coarse step, a periodic n^3 box
+ * in patch-group order [G][5][16][16][16], n a multiple of 16):
+ *  - refluxing: a coarse cell that no fine group covers, next across a face
+ *    to one that a fine group covers, had its update formed with the coarse
+ *    flux Fc of that face; it is corrected to the mean Ff of the four fine
+ *    fluxes on that face: U -= dt/dh (Ff - Fc) when the fine side is its +
+ *    side, U += dt/dh (Ff - Fc) when it is its - side;
+ *  - restriction: each covered coarse cell becomes the mean of its 8
+ *    children.
+ * The fine level has ratio 2; fine group f (fine_layout[f] = (unused, ox,
+ * oy, oz), origins on the fine grid's 16-cell grid, so each fine group
+ * covers one 8^3 coarse patch) has interiors fine[f][5][16][16][16] and face
+ * fluxes fine_flux[f][3][2][5][16][16] averaged over its sub-steps (weights
+ * dt_sub / dt, see hydro_accumulate).  fine_map is the fine level's group
+ * map from hydro_build_group_map(fine_layout, n_fine, n / 8, 1, ...).
+ * coarse_flux [G][3][3][5][16][16] holds the coarse step's fluxes on every
+ * patch face (faces -, + and the mid plane, i.e. a solve with
+ * HYDRO_FLUX_MID).  dt, dh: the coarse step and cell size.  The correction
+ * conserves the domain totals of a coarse step and its fine sub-steps.
+ * flags: HYDRO_F64 or 0.  Errors: HYDRO_EINVAL, HYDRO_EALIAS (coarse
+ * overlaps an input), HYDRO_EHIP.
+ */
+int hydro_amr_correct(void* coarse, int n, const void* coarse_flux, const void* fine, const int* fine_layout,
+                      int n_fine, const int* fine_map, const void* fine_flux, double dt, double dh, int flags,
+                      void* stream);
+
+/*
+ * acc[i] += w * x[i] for n elements (float, or double with HYDRO_F64),
+ * evaluated in FP64: the sub-step average of fine face fluxes for
+ * hydro_amr_correct.  acc == x is allowed; a partial overlap is
+ * HYDRO_EALIAS.
+ */
+int hydro_accumulate(void* acc, const void* x, double w, long long n, int flags, void* stream);
+
 /* One segment of a batched launch: `count` groups advanced by
  * dt = (*dt) * dt_scale with cell size dh.  `dt` points to a device double,
  * so the time step can be produced on the device (e.g. by hydro_cfl_dt) and

@@ -581,6 +581,50 @@ int hydro_fill_groups_amr(const void* fine, const int* layout, int n_groups, con
   return 0;
 }
 
+int hydro_amr_correct(void* coarse, int n, const void* coarse_flux, const void* fine, const int* fine_layout,
+                      int n_fine, const int* fine_map, const void* fine_flux, double dt, double dh, int flags,
+                      void* stream) {
+  g_err[0] = 0;
+  if (n <= 0 || n % 16 || n > 8192) return fail(HYDRO_EINVAL, "coarse box size must be a positive multiple of 16");
+  if (n_fine < 0) return fail(HYDRO_EINVAL, "n_fine < 0");
+  if (!(dt > 0.0) || !isfinite(dt) || !(dh > 0.0) || !isfinite(dh))
+    return fail(HYDRO_EINVAL, "dt and dh must be positive and finite");
+  if (flags & ~HYDRO_F64) return fail(HYDRO_EINVAL, "only HYDRO_F64 is accepted");
+  if (n_fine == 0) return 0;
+  if (!coarse || !coarse_flux || !fine || !fine_layout || !fine_map || !fine_flux)
+    return fail(HYDRO_EINVAL, "null pointer");
+  const size_t esz = (flags & HYDRO_F64) ? 8 : 4;
+  const size_t gc = (size_t)(n / 16) * (n / 16) * (n / 16);
+  const size_t ub = gc * 5 * 4096 * esz, cfb = gc * 3 * 3 * 5 * 256 * esz;
+  const size_t fb = (size_t)n_fine * 5 * 4096 * esz, ffb = (size_t)n_fine * 3 * 2 * 5 * 256 * esz;
+  if (overlap(coarse, ub, coarse_flux, cfb) || overlap(coarse, ub, fine, fb) || overlap(coarse, ub, fine_flux, ffb))
+    return fail(HYDRO_EALIAS, "the coarse box overlaps an input");
+  hipStream_t st = (hipStream_t)stream;
+  const double dtdh = dt / dh;
+  hipError_t e = (flags & HYDRO_F64)
+                     ? hy::launch_amr_correct((double*)coarse, n, (const double*)coarse_flux, (const double*)fine,
+                                              fine_layout, n_fine, fine_map, (const double*)fine_flux, dtdh, st)
+                     : hy::launch_amr_correct((float*)coarse, n, (const float*)coarse_flux, (const float*)fine,
+                                              fine_layout, n_fine, fine_map, (const float*)fine_flux, dtdh, st);
+  if (e != hipSuccess) return hip_fail(e, "coarse-grid correction");
+  return 0;
+}
+
+int hydro_accumulate(void* acc, const void* x, double w, long long n, int flags, void* stream) {
+  g_err[0] = 0;
+  if (n < 0) return fail(HYDRO_EINVAL, "n < 0");
+  if (!isfinite(w)) return fail(HYDRO_EINVAL, "weight must be finite");
+  if (flags & ~HYDRO_F64) return fail(HYDRO_EINVAL, "only HYDRO_F64 is accepted");
+  if (n == 0) return 0;
+  if (!acc || !x) return fail(HYDRO_EINVAL, "null pointer");
+  const size_t b = (size_t)n * ((flags & HYDRO_F64) ? 8 : 4);
+  if (acc != x && overlap(acc, b, x, b)) return fail(HYDRO_EALIAS, "acc and x overlap partially");
+  hipError_t e = (flags & HYDRO_F64) ? hy::launch_axpy((double*)acc, (const double*)x, w, n, (hipStream_t)stream)
+                                     : hy::launch_axpy((float*)acc, (const float*)x, w, n, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "accumulate");
+  return 0;
+}
+
 int hydro_get_diag(struct hydro_diag* out, int reset, void* stream) {
   g_err[0] = 0;
   if (!out) return fail(HYDRO_EINVAL, "null output");

@@ -397,6 +397,154 @@ template hipError_t launch_fill_amr<float>(const float*, const int*, int, const 
 template hipError_t launch_fill_amr<double>(const double*, const int*, int, const int*, int, int, const double*,
                                             const double*, int, const double*, int, double*, hipStream_t);
 
+// ---------------------------------------------------------------------------
+// Coarse-grid correction after a coarse step (Sec. 2 step 5, Sec. 4.3): the
+// coarse level is a periodic n^3 box in patch-group order, the fine level
+// has ratio 2 and its groups (fine-grid origins on the 16-cell grid) each
+// cover one 8^3 coarse patch; fmap is the fine level's group map (n / 8
+// groups per side).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int fine_owner(const int* fmap, int nf, int ngf, int cx, int cy, int cz) {
+  const int o = fmap[((long long)(cz >> 3) * ngf + (cy >> 3)) * ngf + (cx >> 3)];
+  return (o >= 0 && o < nf) ? o : -1;
+}
+
+// Refluxing, one thread per coarse cell.  An uncovered cell next to a
+// covered one across a face replaces the coarse flux of that face (stored
+// by the coarse step on the patch faces: group faces -, + and the mid plane)
+// by the mean of the four fine fluxes on it: U -= dt/dh (Ff - Fc) when the
+// fine cell lies on its + side, += on its - side, in the order x, y, z and
+// -, +.  No contraction: the same FP64 expression as a plain evaluation.
+template <typename T>
+__global__ void __launch_bounds__(256) reflux_kernel(T* __restrict__ U, int n, const T* __restrict__ cflux,
+                                                     const int* __restrict__ fmap, int nf,
+                                                     const T* __restrict__ fflux, const int4* __restrict__ flayout,
+                                                     double dtdh) {
+#pragma clang fp contract(off)
+  const int ng = n >> 4, ngf = n >> 3;
+  const long long total = (long long)ng * ng * ng * 4096;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
+       t += (long long)gridDim.x * blockDim.x) {
+    const long long G = t >> 12;
+    const int l = (int)(t & 4095);
+    const int lx = l & 15, ly = (l >> 4) & 15, lz = l >> 8;
+    const int gx = (int)(G % ng), gy = (int)((G / ng) % ng), gz = (int)(G / ((long long)ng * ng));
+    const int c[3] = {gx * 16 + lx, gy * 16 + ly, gz * 16 + lz};
+    if (fine_owner(fmap, nf, ngf, c[0], c[1], c[2]) >= 0) continue;
+    const int loc[3] = {lx, ly, lz};
+    double u[5];
+    bool touched = false;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) u[v] = (double)U[(G * 5 + v) * 4096 + l];
+    for (int d = 0; d < 3; ++d) {
+      // transverse coordinates (slow, fast) of a d-face: x (z, y), y (z, x), z (y, x)
+      const int ts = d == 2 ? 1 : 2, tf = d == 0 ? 1 : 0;
+      for (int side = -1; side <= 1; side += 2) {
+        int b[3] = {c[0], c[1], c[2]};
+        b[d] += side;
+        b[d] += b[d] < 0 ? n : 0;
+        b[d] -= b[d] >= n ? n : 0;
+        const int F = fine_owner(fmap, nf, ngf, b[0], b[1], b[2]);
+        if (F < 0) continue;
+        const int slot = side > 0 ? (loc[d] == 15 ? 1 : (loc[d] == 7 ? 2 : -1)) : (loc[d] == 0 ? 0 : (loc[d] == 8 ? 2 : -1));
+        if (slot < 0) continue;  // cannot happen: fine groups cover whole coarse patches
+        const int4 o = flayout[F];
+        const int fo[3] = {o.y, o.z, o.w};
+        const int fs0 = 2 * (c[ts] - (fo[ts] >> 1)), ff0 = 2 * (c[tf] - (fo[tf] >> 1));
+        if (fs0 < 0 || fs0 > 14 || ff0 < 0 || ff0 > 14) continue;  // layout disagrees with the map
+        const int fslot = side > 0 ? 0 : 1;
+        const double sg = side > 0 ? -1.0 : 1.0;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          const double Fc = (double)cflux[((((G * 3 + d) * 3 + slot) * 5 + v) * 16 + loc[ts]) * 16 + loc[tf]];
+          const T* f = fflux + ((((long long)F * 3 + d) * 2 + fslot) * 5 + v) * 256;
+          double Ff = 0.0;
+          Ff += (double)f[fs0 * 16 + ff0];
+          Ff += (double)f[fs0 * 16 + ff0 + 1];
+          Ff += (double)f[(fs0 + 1) * 16 + ff0];
+          Ff += (double)f[(fs0 + 1) * 16 + ff0 + 1];
+          Ff *= 0.25;
+          u[v] += sg * dtdh * (Ff - Fc);
+        }
+        touched = true;
+      }
+    }
+    if (touched) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) U[(G * 5 + v) * 4096 + l] = (T)u[v];
+    }
+  }
+}
+
+// Restriction: one workgroup per fine group, one thread per covered coarse
+// cell (8^3); only the group that the map names at its position writes.
+template <typename T>
+__global__ void __launch_bounds__(512) restrict_kernel(T* __restrict__ U, int n, const T* __restrict__ fine,
+                                                       const int4* __restrict__ flayout, const int* __restrict__ fmap,
+                                                       int nf) {
+#pragma clang fp contract(off)
+  const int F = blockIdx.x;
+  const int4 o = flayout[F];
+  const int nfine = 2 * n;
+  if (o.y < 0 || o.z < 0 || o.w < 0 || o.y >= nfine || o.z >= nfine || o.w >= nfine || ((o.y | o.z | o.w) & 15))
+    return;
+  const int cx0 = o.y >> 1, cy0 = o.z >> 1, cz0 = o.w >> 1;
+  if (fine_owner(fmap, nf, n >> 3, cx0, cy0, cz0) != F) return;
+  const int i = threadIdx.x & 7, j = (threadIdx.x >> 3) & 7, k = threadIdx.x >> 6;
+  const int cx = cx0 + i, cy = cy0 + j, cz = cz0 + k;
+  const int ng = n >> 4;
+  const long long G = ((long long)(cz >> 4) * ng + (cy >> 4)) * ng + (cx >> 4);
+  const int l = ((cz & 15) * 16 + (cy & 15)) * 16 + (cx & 15);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const T* f = fine + ((long long)F * 5 + v) * 4096;
+    double s = 0.0;
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+      for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) s += (double)f[((2 * k + dz) * 16 + 2 * j + dy) * 16 + 2 * i + dx];
+    U[(G * 5 + v) * 4096 + l] = (T)(0.125 * s);
+  }
+}
+
+template <typename T>
+hipError_t launch_amr_correct(T* U, int n, const T* cflux, const T* fine, const int* flayout, int nf,
+                              const int* fmap, const T* fflux, double dtdh, hipStream_t st) {
+  const long long cells = (long long)n * n * n;
+  long long blocks = (cells + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  reflux_kernel<T><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(U, n, cflux, fmap, nf, fflux, (const int4*)flayout,
+                                                                  dtdh);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || nf == 0) return e;
+  restrict_kernel<T><<<dim3((unsigned)nf), dim3(512), 0, st>>>(U, n, fine, (const int4*)flayout, fmap, nf);
+  return hipGetLastError();
+}
+template hipError_t launch_amr_correct<float>(float*, int, const float*, const float*, const int*, int, const int*,
+                                              const float*, double, hipStream_t);
+template hipError_t launch_amr_correct<double>(double*, int, const double*, const double*, const int*, int,
+                                               const int*, const double*, double, hipStream_t);
+
+// acc += w * x, elementwise (the weighted sum of fine fluxes over sub-steps).
+template <typename T>
+__global__ void __launch_bounds__(256) axpy_kernel(T* __restrict__ acc, const T* __restrict__ x, double w, long long n) {
+#pragma clang fp contract(off)
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x)
+    acc[t] = (T)((double)acc[t] + w * (double)x[t]);
+}
+template <typename T>
+hipError_t launch_axpy(T* acc, const T* x, double w, long long n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  long long blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  axpy_kernel<T><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(acc, x, w, n);
+  return hipGetLastError();
+}
+template hipError_t launch_axpy<float>(float*, const float*, double, long long, hipStream_t);
+template hipError_t launch_axpy<double>(double*, const double*, double, long long, hipStream_t);
+
 template <typename T>
 hipError_t launch_fill_interp(const T* coarse, int cn, const int* layout, long long n_groups, int g, double base_dh,
                               T* out, hipStream_t st) {

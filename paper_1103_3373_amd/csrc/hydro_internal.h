@@ -98,6 +98,11 @@ hipError_t launch_fill_periodic(const T* box, int nx, int ny, int nz, int g, int
 hipError_t launch_group_map(const int* layout, int n_groups, int ng0, int n_levels, long long map_len, int* map,
                             hipStream_t st);
 template <typename T>
+hipError_t launch_amr_correct(T* U, int n, const T* cflux, const T* fine, const int* flayout, int nf,
+                              const int* fmap, const T* fflux, double dtdh, hipStream_t st);
+template <typename T>
+hipError_t launch_axpy(T* acc, const T* x, double w, long long n, hipStream_t st);
+template <typename T>
 hipError_t launch_fill_amr(const T* fine, const int* layout, int n_groups, const int* map, int ng0, int n_levels,
                            const T* c0, const T* c1, int cn, const double* alpha, int g, T* out, hipStream_t st);
 template <typename T>

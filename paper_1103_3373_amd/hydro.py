@@ -24,7 +24,7 @@ F64, CHAR, FLUX_MID, PLAIN, ROE_FB_HLLC, BOX_GROUPED, BOX_SEGS = 0x01, 0x02, 0x0
 EXPORTS = (
     "hydro_ghost_width", "hydro_solve_groups", "hydro_cfl_dt", "hydro_conserved_sums", "hydro_cfl_dt_sums",
     "hydro_fill_ghosts_periodic", "hydro_fill_groups_interp", "hydro_group_map_len", "hydro_build_group_map",
-    "hydro_fill_groups_amr", "hydro_solve_batch", "hydro_autotune",
+    "hydro_fill_groups_amr", "hydro_amr_correct", "hydro_accumulate", "hydro_solve_batch", "hydro_autotune",
     "hydro_set_launch_shape", "hydro_step_box", "hydro_cfl_dt_batch",
     "hydro_get_diag", "hydro_last_error", "hydro_shutdown",
 )
@@ -84,6 +84,10 @@ def lib() -> ctypes.CDLL:
     L.hydro_build_group_map.restype = i
     L.hydro_fill_groups_amr.argtypes = [P, P, i, P, i, i, P, P, i, ctypes.POINTER(d), i, i, P, P]
     L.hydro_fill_groups_amr.restype = i
+    L.hydro_amr_correct.argtypes = [P, i, P, P, P, i, P, P, d, d, i, P]
+    L.hydro_amr_correct.restype = i
+    L.hydro_accumulate.argtypes = [P, P, d, ll, i, P]
+    L.hydro_accumulate.restype = i
     L.hydro_step_box.argtypes = [P, P, P, i, i, i, P, d, d, d, i, i, i, i, i, P]
     L.hydro_step_box.restype = i
     L.hydro_cfl_dt_batch.argtypes = [P, i, ll, d, d, i, P]
@@ -273,6 +277,33 @@ def fill_groups_amr(fine, layout, gmap, ng0, alpha, coarse0, coarse1, g, out=Non
         _ptr(fine), _ptr(layout), n, _ptr(gmap), int(ng0), len(alpha), _ptr(coarse0), _ptr(coarse1),
         coarse0.shape[1], al, g, _dtype_flag(fine), _ptr(out), _stream(stream)))
     return out
+
+
+def amr_correct(coarse, n, coarse_flux, fine, fine_layout, fine_map, fine_flux, dt, dh, stream=None):
+    """Coarse-grid correction in place on the coarse box [G,5,16,16,16]
+    (patch-group order, n^3 cells): refluxing at the coarse-fine faces, then
+    restriction of the refined patches."""
+    G = (n // 16) ** 3
+    nf = fine_layout.shape[0]
+    _require(coarse, "coarse", (G, 5, 16, 16, 16))
+    _require(coarse_flux, "coarse_flux", (G, 3, 3, 5, 16, 16), coarse.dtype)
+    _require(fine, "fine", (nf, 5, 16, 16, 16), coarse.dtype)
+    _require(fine_layout, "fine_layout", dtype=torch.int32)
+    _require(fine_map, "fine_map", (group_map_len(n // 8, 1),), torch.int32)
+    _require(fine_flux, "fine_flux", (nf, 3, 2, 5, 16, 16), coarse.dtype)
+    _check("hydro_amr_correct", lib().hydro_amr_correct(
+        _ptr(coarse), n, _ptr(coarse_flux), _ptr(fine), _ptr(fine_layout), nf, _ptr(fine_map), _ptr(fine_flux),
+        float(dt), float(dh), _dtype_flag(coarse), _stream(stream)))
+    return coarse
+
+
+def accumulate(acc, x, w, stream=None):
+    """acc += w * x elementwise (evaluated in FP64)."""
+    _require(acc, "acc")
+    _require(x, "x", tuple(acc.shape), acc.dtype)
+    _check("hydro_accumulate", lib().hydro_accumulate(_ptr(acc), _ptr(x), float(w), acc.numel(),
+                                                      _dtype_flag(acc), _stream(stream)))
+    return acc
 
 
 def make_spec(scheme, recon, riemann, limiter=VANLEER, *, gamma, char=False, f64=False, flux_mid=False,

@@ -144,3 +144,24 @@ def test_amr_preparation_validation(L):
     assert call(fine=P(0)) == EINVAL
     assert call(out=P(0x10000000 + 64)) == EALIAS
     assert call(n=0) == 0
+
+
+def test_amr_correct_validation(L):
+    """Argument checks of the coarse-grid correction and accumulate (host only)."""
+    EINVAL, EALIAS = -1, -4
+    P = ctypes.c_void_p
+    c, cf, f, lay, m, ff = P(0x10000000), P(0x20000000), P(0x30000000), P(0x1000), P(0x2000), P(0x40000000)
+    fn = L.hydro_amr_correct
+    assert fn(c, 24, cf, f, lay, 2, m, ff, 1e-3, 1.0 / 32, 0, None) == EINVAL      # n not a multiple of 16
+    assert fn(c, 32, cf, f, lay, -1, m, ff, 1e-3, 1.0 / 32, 0, None) == EINVAL     # n_fine < 0
+    assert fn(c, 32, cf, f, lay, 2, m, ff, 0.0, 1.0 / 32, 0, None) == EINVAL       # dt
+    assert fn(c, 32, cf, f, lay, 2, m, ff, 1e-3, 1.0 / 32, 0x02, None) == EINVAL   # flags
+    assert fn(c, 32, cf, P(0), lay, 2, m, ff, 1e-3, 1.0 / 32, 0, None) == EINVAL   # null
+    assert fn(c, 32, P(0x10000000 + 4096), f, lay, 2, m, ff, 1e-3, 1.0 / 32, 0, None) == EALIAS
+    assert fn(c, 32, cf, f, lay, 0, m, ff, 1e-3, 1.0 / 32, 0, None) == 0
+    acc = L.hydro_accumulate
+    assert acc(P(0x1000), P(0x2000), 0.5, -1, 0, None) == EINVAL
+    assert acc(P(0x1000), P(0x2000), float("nan"), 4, 0, None) == EINVAL
+    assert acc(P(0x1000), P(0x1000 + 4), 0.5, 4, 0, None) == EALIAS
+    assert acc(P(0), P(0x2000), 0.5, 4, 0, None) == EINVAL
+    assert acc(P(0x1000), P(0x2000), 0.5, 0, 0, None) == 0

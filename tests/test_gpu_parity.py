@@ -361,3 +361,92 @@ def test_amr_fill_full_level_is_periodic_fill(H):
     got = H.fill_groups_amr(_dev(fine, torch.float64), lay_d, gmap, 2, [0.5], c, c, 3).cpu().numpy()
     want = H.fill_ghosts_periodic(_dev(box, torch.float64), 3).cpu().numpy()
     np.testing.assert_array_equal(got, want)
+
+
+def _fine_layout_32():
+    # Fine-grid origins (64^3 fine grid over a 32^3 coarse box): two adjacent
+    # groups, one across the periodic boundary from them, one isolated.
+    return np.array([[0, 16, 16, 16], [0, 32, 16, 16], [0, 48, 16, 16], [0, 0, 48, 0]], dtype=np.int32)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_amr_correct_matches_oracle(H, dtype):
+    """Refluxing and restriction on random data against the oracle: FP64 bit
+    for bit (same expressions in the same order), FP32 to its rounding."""
+    rng = np.random.default_rng(51)
+    n = 32
+    lay = _fine_layout_32()
+    coarse = rng.standard_normal((8, 5, 16, 16, 16)) + 3.0
+    cflux = rng.standard_normal((8, 3, 3, 5, 16, 16))
+    fine = rng.standard_normal((4, 5, 16, 16, 16)) + 3.0
+    fflux = rng.standard_normal((4, 3, 2, 5, 16, 16))
+    if dtype == torch.float32:
+        coarse, cflux, fine, fflux = (a.astype(np.float32).astype(np.float64) for a in (coarse, cflux, fine, fflux))
+    dt, dh = 2e-3, 1.0 / n
+    want = O.amr_correct(coarse, (n, n, n), cflux, fine, lay, fflux, dt, dh)
+    lay_d = torch.from_numpy(lay).cuda()
+    fmap = H.build_group_map(lay_d, n // 8, 1)
+    got = _dev(coarse, dtype)
+    H.amr_correct(got, n, _dev(cflux, dtype), _dev(fine, dtype), lay_d, fmap, _dev(fflux, dtype), dt, dh)
+    got = got.cpu().numpy().astype(np.float64)
+    if dtype == torch.float64:
+        np.testing.assert_array_equal(got, want)
+    else:
+        assert scaled_max_err(got, want) <= 2e-7
+    assert not np.array_equal(want, coarse)
+
+
+def test_amr_cycle_conserves_on_gpu(H):
+    """A whole two-level step on the GPU in FP64: the coarse step (fluxes on
+    every patch face), two fine sub-steps prepared by the AMR fill at the
+    sub-step times, the flux average, then the coarse-grid correction.  The
+    domain totals are conserved to round-off and the result matches the
+    same cycle run by the oracle."""
+    gamma = 1.4
+    n = 32
+    dh = 1.0 / n
+    box = W.lognormal_blast_box(n, gamma=gamma, seed=17, radius_cells=3)
+    lay = _fine_layout_32()
+    fine0 = np.stack([np.repeat(np.repeat(np.repeat(
+        box[:, o[3] // 2:o[3] // 2 + 8, o[2] // 2:o[2] // 2 + 8, o[1] // 2:o[1] // 2 + 8], 2, 1), 2, 2), 2, 3)
+        for o in lay])
+    g = 3
+    dt = O.cfl_dt(box, dh, gamma, 0.4)
+    # Oracle cycle.
+    cg, cflux = O.solve_groups(O.fill_ghosts_periodic(box, g), g, dt, dh, gamma, 2, 1, 1, 1,
+                               O.F_CHAR | O.F_FLUX_MID, want_flux=True)
+    new_box = W.groups_to_box(cg, n, n, n)
+    fine, fflux = fine0, np.zeros((4, 3, 2, 5, 16, 16))
+    for s in range(2):
+        pad = O.fill_groups_amr(fine, lay, 4, [0.5 * s], box, new_box, g)
+        fine, fl = O.solve_groups(pad, g, 0.5 * dt, 0.5 * dh, gamma, 2, 1, 1, 1, O.F_CHAR, want_flux=True)
+        fflux += 0.5 * fl
+    want = O.amr_correct(cg, (n, n, n), cflux, fine, lay, fflux, dt, dh)
+    # GPU cycle.
+    f64 = torch.float64
+    c_old = _dev(box, f64)
+    grp = H.fill_ghosts_periodic(c_old, g)
+    c_new = torch.empty((8, 5, 16, 16, 16), dtype=f64, device="cuda")
+    c_flux = torch.empty((8, 3, 3, 5, 16, 16), dtype=f64, device="cuda")
+    H.solve_groups(grp, c_new, c_flux, dt=dt, dh=dh, gamma=gamma, scheme=2, recon=1, riemann=1, char=True,
+                   flux_mid=True)
+    c_new_box = torch.from_numpy(W.groups_to_box(c_new.cpu().numpy(), n, n, n)).cuda()
+    lay_d = torch.from_numpy(lay).cuda()
+    fmap = H.build_group_map(lay_d, n // 8, 1)
+    amap = H.build_group_map(lay_d, 4, 1)
+    f_state = _dev(fine0, f64)
+    f_acc = torch.zeros((4, 3, 2, 5, 16, 16), dtype=f64, device="cuda")
+    f_flux = torch.empty_like(f_acc)
+    for s in range(2):
+        pad = H.fill_groups_amr(f_state, lay_d, amap, 4, [0.5 * s], c_old, c_new_box, g)
+        f_next = torch.empty_like(f_state)
+        H.solve_groups(pad, f_next, f_flux, dt=0.5 * dt, dh=0.5 * dh, gamma=gamma, scheme=2, recon=1, riemann=1,
+                       char=True)
+        H.accumulate(f_acc, f_flux, 0.5)
+        f_state = f_next
+    H.amr_correct(c_new, n, c_flux, f_state, lay_d, fmap, f_acc, dt, dh)
+    got = c_new.cpu().numpy()
+    assert scaled_max_err(got, want) <= 1e-12
+    t0 = box.reshape(5, -1).sum(1)
+    t1 = W.groups_to_box(got, n, n, n).reshape(5, -1).sum(1)
+    assert np.abs(t1 - t0).max() <= 1e-13 * np.abs(t0).max()
