@@ -216,7 +216,9 @@ int hydro_fill_groups_amr(const void* fine, const int* layout, int n_groups, con
  * covers one 8^3 coarse patch) has interiors fine[f][5][16][16][16] and face
  * fluxes fine_flux[f][3][2][5][16][16] averaged over its sub-steps (weights
  * dt_sub / dt, see hydro_accumulate).  fine_map is the fine level's group
- * map from hydro_build_group_map(fine_layout, n_fine, n / 8, 1, ...).
+ * map from hydro_build_group_map(fine_layout, n_fine, n / 8, 1, ...), which
+ * takes only entries whose level field is 0 (fine groups with another level
+ * entry are left out of the map and so neither reflux nor restrict).
  * coarse_flux [G][3][3][5][16][16] holds the coarse step's fluxes on every
  * patch face (faces -, + and the mid plane, i.e. a solve with
  * HYDRO_FLUX_MID).  dt, dh: the coarse step and cell size.  The correction

@@ -421,58 +421,63 @@ __global__ void __launch_bounds__(256) reflux_kernel(T* __restrict__ U, int n, c
                                                      const T* __restrict__ fflux, const int4* __restrict__ flayout,
                                                      double dtdh) {
 #pragma clang fp contract(off)
+  // 16 workgroups of 256 threads per coarse group: the group and its
+  // coordinates are uniform over a workgroup.
   const int ng = n >> 4, ngf = n >> 3;
-  const long long total = (long long)ng * ng * ng * 4096;
-  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
-       t += (long long)gridDim.x * blockDim.x) {
-    const long long G = t >> 12;
-    const int l = (int)(t & 4095);
-    const int lx = l & 15, ly = (l >> 4) & 15, lz = l >> 8;
-    const int gx = (int)(G % ng), gy = (int)((G / ng) % ng), gz = (int)(G / ((long long)ng * ng));
-    const int c[3] = {gx * 16 + lx, gy * 16 + ly, gz * 16 + lz};
-    if (fine_owner(fmap, nf, ngf, c[0], c[1], c[2]) >= 0) continue;
-    const int loc[3] = {lx, ly, lz};
-    double u[5];
-    bool touched = false;
+  const long long G = blockIdx.x >> 4;
+  const int l = (int)(((blockIdx.x & 15) << 8) | threadIdx.x);
+  const int lx = l & 15, ly = (l >> 4) & 15, lz = l >> 8;
+  const int gx = (int)(G % ng), gy = (int)((G / ng) % ng), gz = (int)(G / ((long long)ng * ng));
+  // Fine groups cover whole 8^3 coarse patches, so only cells on a patch
+  // face (local index 0, 7, 8 or 15 along some axis) can border one.
+  const int loc[3] = {lx, ly, lz};
+  auto edge = [](int q) { return (q & 7) == 0 || (q & 7) == 7; };
+  if (!edge(lx) && !edge(ly) && !edge(lz)) return;
+  const int c[3] = {gx * 16 + lx, gy * 16 + ly, gz * 16 + lz};
+  if (fine_owner(fmap, nf, ngf, c[0], c[1], c[2]) >= 0) return;
+  double u[5];
+  bool touched = false;  // U is read at the first correction only
+  for (int d = 0; d < 3; ++d) {
+    // transverse coordinates (slow, fast) of a d-face: x (z, y), y (z, x), z (y, x)
+    const int ts = d == 2 ? 1 : 2, tf = d == 0 ? 1 : 0;
+    for (int side = -1; side <= 1; side += 2) {
+      if ((loc[d] & 7) != (side > 0 ? 7 : 0)) continue;  // not on a patch face on this side
+      int b[3] = {c[0], c[1], c[2]};
+      b[d] += side;
+      b[d] += b[d] < 0 ? n : 0;
+      b[d] -= b[d] >= n ? n : 0;
+      const int F = fine_owner(fmap, nf, ngf, b[0], b[1], b[2]);
+      if (F < 0) continue;
+      const int slot = side > 0 ? (loc[d] == 15 ? 1 : (loc[d] == 7 ? 2 : -1)) : (loc[d] == 0 ? 0 : (loc[d] == 8 ? 2 : -1));
+      if (slot < 0) continue;  // cannot happen: fine groups cover whole coarse patches
+      const int4 o = flayout[F];
+      const int fo[3] = {o.y, o.z, o.w};
+      const int fs0 = 2 * (c[ts] - (fo[ts] >> 1)), ff0 = 2 * (c[tf] - (fo[tf] >> 1));
+      if (fs0 < 0 || fs0 > 14 || ff0 < 0 || ff0 > 14) continue;  // layout disagrees with the map
+      const int fslot = side > 0 ? 0 : 1;
+      const double sg = side > 0 ? -1.0 : 1.0;
+      if (!touched) {
 #pragma unroll
-    for (int v = 0; v < 5; ++v) u[v] = (double)U[(G * 5 + v) * 4096 + l];
-    for (int d = 0; d < 3; ++d) {
-      // transverse coordinates (slow, fast) of a d-face: x (z, y), y (z, x), z (y, x)
-      const int ts = d == 2 ? 1 : 2, tf = d == 0 ? 1 : 0;
-      for (int side = -1; side <= 1; side += 2) {
-        int b[3] = {c[0], c[1], c[2]};
-        b[d] += side;
-        b[d] += b[d] < 0 ? n : 0;
-        b[d] -= b[d] >= n ? n : 0;
-        const int F = fine_owner(fmap, nf, ngf, b[0], b[1], b[2]);
-        if (F < 0) continue;
-        const int slot = side > 0 ? (loc[d] == 15 ? 1 : (loc[d] == 7 ? 2 : -1)) : (loc[d] == 0 ? 0 : (loc[d] == 8 ? 2 : -1));
-        if (slot < 0) continue;  // cannot happen: fine groups cover whole coarse patches
-        const int4 o = flayout[F];
-        const int fo[3] = {o.y, o.z, o.w};
-        const int fs0 = 2 * (c[ts] - (fo[ts] >> 1)), ff0 = 2 * (c[tf] - (fo[tf] >> 1));
-        if (fs0 < 0 || fs0 > 14 || ff0 < 0 || ff0 > 14) continue;  // layout disagrees with the map
-        const int fslot = side > 0 ? 0 : 1;
-        const double sg = side > 0 ? -1.0 : 1.0;
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-          const double Fc = (double)cflux[((((G * 3 + d) * 3 + slot) * 5 + v) * 16 + loc[ts]) * 16 + loc[tf]];
-          const T* f = fflux + ((((long long)F * 3 + d) * 2 + fslot) * 5 + v) * 256;
-          double Ff = 0.0;
-          Ff += (double)f[fs0 * 16 + ff0];
-          Ff += (double)f[fs0 * 16 + ff0 + 1];
-          Ff += (double)f[(fs0 + 1) * 16 + ff0];
-          Ff += (double)f[(fs0 + 1) * 16 + ff0 + 1];
-          Ff *= 0.25;
-          u[v] += sg * dtdh * (Ff - Fc);
-        }
+        for (int v = 0; v < 5; ++v) u[v] = (double)U[(G * 5 + v) * 4096 + l];
         touched = true;
       }
-    }
-    if (touched) {
 #pragma unroll
-      for (int v = 0; v < 5; ++v) U[(G * 5 + v) * 4096 + l] = (T)u[v];
+      for (int v = 0; v < 5; ++v) {
+        const double Fc = (double)cflux[((((G * 3 + d) * 3 + slot) * 5 + v) * 16 + loc[ts]) * 16 + loc[tf]];
+        const T* f = fflux + ((((long long)F * 3 + d) * 2 + fslot) * 5 + v) * 256;
+        double Ff = 0.0;
+        Ff += (double)f[fs0 * 16 + ff0];
+        Ff += (double)f[fs0 * 16 + ff0 + 1];
+        Ff += (double)f[(fs0 + 1) * 16 + ff0];
+        Ff += (double)f[(fs0 + 1) * 16 + ff0 + 1];
+        Ff *= 0.25;
+        u[v] += sg * dtdh * (Ff - Fc);
+      }
     }
+  }
+  if (touched) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) U[(G * 5 + v) * 4096 + l] = (T)u[v];
   }
 }
 
@@ -512,9 +517,7 @@ __global__ void __launch_bounds__(512) restrict_kernel(T* __restrict__ U, int n,
 template <typename T>
 hipError_t launch_amr_correct(T* U, int n, const T* cflux, const T* fine, const int* flayout, int nf,
                               const int* fmap, const T* fflux, double dtdh, hipStream_t st) {
-  const long long cells = (long long)n * n * n;
-  long long blocks = (cells + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
+  const long long blocks = (long long)(n / 16) * (n / 16) * (n / 16) * 16;  // n <= 8192: below 2^31
   reflux_kernel<T><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(U, n, cflux, fmap, nf, fflux, (const int4*)flayout,
                                                                   dtdh);
   hipError_t e = hipGetLastError();
