@@ -53,8 +53,13 @@ extern "C" {
 enum hydro_scheme { HYDRO_MHM = 0, HYDRO_VL = 1, HYDRO_CTU = 2 };
 /* Reconstruction (Sec. 2). */
 enum hydro_recon { HYDRO_PLM = 0, HYDRO_PPM = 1 };
-/* Riemann solvers (Sec. 2).  The exact solver is not built on the GPU. */
-enum hydro_riemann { HYDRO_ROE = 0, HYDRO_HLLC = 1, HYDRO_HLLE = 2 };
+/* Riemann solvers (Sec. 2).  The exact solver (Newton iteration on the
+ * star pressure, then sampling on the face) runs on the plain path only:
+ * hydro_solve_groups takes that path for it, and the fused-only calls
+ * (hydro_solve_batch, hydro_step_box, hydro_autotune) return
+ * HYDRO_EUNSUPPORTED.  With HYDRO_EXACT the first diagnostic counter counts
+ * faces that generate vacuum or do not converge. */
+enum hydro_riemann { HYDRO_ROE = 0, HYDRO_HLLC = 1, HYDRO_HLLE = 2, HYDRO_EXACT = 3 };
 /* Slope limiters (Sec. 2).  The hybrid limiter is the van Leer slope bounded
  * by the generalized minmod slope; theta = 1.5 for both. */
 enum hydro_limiter { HYDRO_LIM_GMINMOD = 0, HYDRO_LIM_VANLEER = 1, HYDRO_LIM_VANALBADA = 2, HYDRO_LIM_HYBRID = 3 };
@@ -67,6 +72,7 @@ enum hydro_limiter { HYDRO_LIM_GMINMOD = 0, HYDRO_LIM_VANLEER = 1, HYDRO_LIM_VAN
 #define HYDRO_ROE_FB_HLLC 0x10  /* Roe fallback flux = HLLC (default HLLE) */
 #define HYDRO_BOX_GROUPED 0x20  /* hydro_fill_ghosts_periodic: box is [G][5][16][16][16] */
 #define HYDRO_BOX_SEGS 0x40     /* hydro_solve_batch: every segment is a periodic box (box == 1) */
+#define HYDRO_ROE_FB_EXACT 0x80 /* Roe fallback flux = exact solver (plain path; Sec. 2) */
 
 /* error codes */
 #define HYDRO_OK 0

@@ -26,7 +26,7 @@ MHM, VL, CTU = 0, 1, 2
 PLM, PPM = 0, 1
 ROE, HLLC, HLLE, EXACT = 0, 1, 2, 3
 GMINMOD, VANLEER, VANALBADA, HYBRID = 0, 1, 2, 3
-F_CHAR, F_FLUX_MID, F_ROE_FB_HLLC = 0x02, 0x04, 0x10
+F_CHAR, F_FLUX_MID, F_ROE_FB_HLLC, F_ROE_FB_EXACT = 0x02, 0x04, 0x10, 0x80
 
 
 def build(force: bool = True) -> None:

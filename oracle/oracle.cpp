@@ -92,7 +92,7 @@ enum { S_MHM = 0, S_VL = 1, S_CTU = 2 };
 enum { R_PLM = 0, R_PPM = 1 };
 enum { RS_ROE = 0, RS_HLLC = 1, RS_HLLE = 2, RS_EXACT = 3 };
 enum { L_GMINMOD = 0, L_VANLEER = 1, L_VANALBADA = 2, L_HYBRID = 3 };
-enum { F_CHAR = 0x02, F_FLUX_MID = 0x04, F_ROE_FB_HLLC = 0x10 };
+enum { F_CHAR = 0x02, F_FLUX_MID = 0x04, F_ROE_FB_HLLC = 0x10, F_ROE_FB_EXACT = 0x80 };
 
 struct V5 {
   real v[5];
@@ -107,7 +107,7 @@ struct Cfg {
   real theta;        // generalized-minmod parameter
   real floor;        // density and pressure floor for face / half-step states
   int scheme, recon, riemann, limiter;
-  bool charlim, fb_hllc;
+  bool charlim, fb_hllc, fb_exact;
 };
 
 struct Stats {
@@ -544,6 +544,7 @@ static V5 riemann_solve(const V5& L, const V5& R, const Cfg& c) {
       V5 F;
       if (flux_roe(L, R, c, F)) return F;
       ++g_stats.roe_fail;
+      if (c.fb_exact) return flux_exact(L, R, c);  // Roe -> exact fallback (Sec. 2)
       return c.fb_hllc ? flux_hllc(L, R, c) : flux_hlle(L, R, c);
     }
   }
@@ -816,6 +817,7 @@ static int make_cfg(Cfg& c, double dt, double dh, double gamma, int scheme, int 
   c.limiter = limiter;
   c.charlim = (flags & F_CHAR) != 0;
   c.fb_hllc = (flags & F_ROE_FB_HLLC) != 0;
+  c.fb_exact = (flags & F_ROE_FB_EXACT) != 0;
   return 0;
 }
 

@@ -30,8 +30,8 @@ int hip_fail(hipError_t e, const char* what) {
   return fail(HYDRO_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-const int kKnownFlags =
-    HYDRO_F64 | HYDRO_CHAR | HYDRO_FLUX_MID | HYDRO_PLAIN | HYDRO_ROE_FB_HLLC | HYDRO_BOX_GROUPED | HYDRO_BOX_SEGS;
+const int kKnownFlags = HYDRO_F64 | HYDRO_CHAR | HYDRO_FLUX_MID | HYDRO_PLAIN | HYDRO_ROE_FB_HLLC | HYDRO_BOX_GROUPED |
+                        HYDRO_BOX_SEGS | HYDRO_ROE_FB_EXACT;
 
 int ghost_width(int scheme, int recon) {
   if (scheme < 0 || scheme > 2 || recon < 0 || recon > 1) return -1;
@@ -154,8 +154,7 @@ hy::Phys<T> make_phys(double dt, double dh, double gamma, int limiter, int flags
 
 int check_options(int scheme, int recon, int riemann, int limiter, int flags) {
   if (ghost_width(scheme, recon) < 0) return fail(HYDRO_EINVAL, "bad scheme %d or reconstruction %d", scheme, recon);
-  if (riemann == 3) return fail(HYDRO_EUNSUPPORTED, "the exact Riemann solver is not built on the GPU");
-  if (riemann < 0 || riemann > 2) return fail(HYDRO_EINVAL, "bad riemann %d", riemann);
+  if (riemann < 0 || riemann > 3) return fail(HYDRO_EINVAL, "bad riemann %d", riemann);
   if (limiter < 0 || limiter > 3) return fail(HYDRO_EINVAL, "bad limiter %d", limiter);
   if (flags & ~kKnownFlags) return fail(HYDRO_EINVAL, "unknown flag bits 0x%x", flags & ~kKnownFlags);
   return 0;
@@ -281,8 +280,10 @@ int hydro_solve_groups(const void* in, void* out, void* flux_out, int n_groups, 
   if (int rc = device_state(&ds)) return rc;
   Workspace& w = ds->ws[st];
 
-  const bool plain = (flags & HYDRO_PLAIN) || !hy::fused_supported(scheme, reconstruction, riemann,
-                                                                   (flags & HYDRO_CHAR) ? 1 : 0);
+  // The exact solver (riemann 3) and the Roe -> exact fallback run on the
+  // plain path only.
+  const bool plain = (flags & (HYDRO_PLAIN | HYDRO_ROE_FB_EXACT)) ||
+                     !hy::fused_supported(scheme, reconstruction, riemann, (flags & HYDRO_CHAR) ? 1 : 0);
   if (plain) {
     int grid = n_groups < kPlainGridMax ? n_groups : kPlainGridMax;
     const long stride = 50L * N * N * N;
@@ -290,11 +291,13 @@ int hydro_solve_groups(const void* in, void* out, void* flux_out, int n_groups, 
     hipError_t e;
     if (f64) {
       hy::PlainArgs<double> a{(const double*)in, (double*)out, (double*)flux_out, n_groups, g, N, nf,
-                              make_phys<double>(dt, dh, gamma, limiter, flags), (double*)w.plain, stride, ds->diag};
+                              make_phys<double>(dt, dh, gamma, limiter, flags), (double*)w.plain, stride, ds->diag,
+                              (flags & HYDRO_ROE_FB_EXACT) ? 1 : 0};
       e = hy::launch_plain(a, scheme, reconstruction, riemann, grid, st);
     } else {
       hy::PlainArgs<float> a{(const float*)in, (float*)out, (float*)flux_out, n_groups, g, N, nf,
-                             make_phys<float>(dt, dh, gamma, limiter, flags), (float*)w.plain, stride, ds->diag};
+                             make_phys<float>(dt, dh, gamma, limiter, flags), (float*)w.plain, stride, ds->diag,
+                             (flags & HYDRO_ROE_FB_EXACT) ? 1 : 0};
       e = hy::launch_plain(a, scheme, reconstruction, riemann, grid, st);
     }
     if (e != hipSuccess) return hip_fail(e, "plain solver launch");
@@ -317,6 +320,7 @@ int hydro_solve_batch(const struct hydro_seg* segs, int n_segs, long long n_grou
   if (!spec) return fail(HYDRO_EINVAL, "null spec");
   if (int rc = check_options(spec->scheme, spec->reconstruction, spec->riemann, spec->limiter, spec->flags)) return rc;
   if (spec->flags & HYDRO_PLAIN) return fail(HYDRO_EINVAL, "HYDRO_PLAIN is not a batched path");
+  if (spec->flags & HYDRO_ROE_FB_EXACT) return fail(HYDRO_EUNSUPPORTED, "the exact fallback runs on the plain path only");
   if (!(spec->gamma > 1.0) || !isfinite(spec->gamma)) return fail(HYDRO_EINVAL, "gamma must exceed 1");
   if (n_groups_total < 0 || n_segs < 0) return fail(HYDRO_EINVAL, "negative sizes");
   if (n_groups_total == 0) return 0;
@@ -353,6 +357,7 @@ int hydro_step_box(const void* box_in, void* box_out, void* flux_out, int nx, in
   g_err[0] = 0;
   if (int rc = check_options(scheme, reconstruction, riemann, limiter, flags)) return rc;
   if (flags & HYDRO_PLAIN) return fail(HYDRO_EINVAL, "HYDRO_PLAIN is not a box path");
+  if (flags & HYDRO_ROE_FB_EXACT) return fail(HYDRO_EUNSUPPORTED, "the exact fallback runs on the plain path only");
   if (!box_in || !box_out || !dt_dev) return fail(HYDRO_EINVAL, "null pointer");
   if (nx <= 0 || ny <= 0 || nz <= 0 || nx % 16 || ny % 16 || nz % 16)
     return fail(HYDRO_EINVAL, "box sizes must be positive multiples of 16");

@@ -35,6 +35,7 @@ struct PlainArgs {
   T* ws;           // per-workgroup global temporaries
   long ws_stride;  // elements per workgroup (50 N^3)
   unsigned long long* diag;  // [0] Roe fallbacks, [1] floor activations
+  int roe_fb_exact;          // Roe failures take the exact flux
 };
 
 hipError_t launch_plain(const PlainArgs<float>& a, int scheme, int recon, int riemann, int grid, hipStream_t st);

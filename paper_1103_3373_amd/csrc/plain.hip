@@ -11,6 +11,7 @@
 // group, so the interior 16^3 cells are exact for the ghost width chosen.
 #include "hydro_internal.h"
 #include "hydro_math.hpp"
+#include "riemann_exact.hpp"
 
 namespace hy {
 
@@ -44,8 +45,32 @@ struct PlainCtx {
   T* Wm[3];       // [5][nc] left-face state of each cell, lab frame
   T* Wp[3];       // [5][nc] right-face state
   T* F[3];        // [5][nc] flux at face i+1/2 stored at i, lab frame
+  int roe_fb_exact;
   HY_DEV long at(int i, int j, int k) const { return ((long)k * N + j) * N + i; }
 };
+
+// Riemann solver of the plain path: RS = 3 is the exact solver; with
+// roe_fb_exact a face where the Roe linearization fails (counted in *fails)
+// takes the exact flux instead of the HLLE/HLLC fallback.
+template <int RS, typename T>
+HY_DEV V5<T> plain_solve(const V5<T>& L, const V5<T>& R, const Phys<T>& ph, int roe_fb_exact, int* fails) {
+  if constexpr (RS == 3) {
+    return exact_flux(L, R, ph, fails);
+  } else if constexpr (RS == 0) {
+    int f = 0;
+    V5<T> F = riemann<0>(L, R, ph, &f);
+    if (f) {
+      *fails += f;
+      if (roe_fb_exact) {
+        int ignored = 0;
+        F = exact_flux(L, R, ph, &ignored);
+      }
+    }
+    return F;
+  } else {
+    return riemann<RS>(L, R, ph, fails);
+  }
+}
 
 template <typename T> HY_DEV V5<T> ld(const T* a, long nc, long q) {
   V5<T> v;
@@ -100,7 +125,7 @@ HY_DEV Box3 plain_riemann(const PlainCtx<T>& c, const T* SL, const T* SR, Box3 c
     const long q = c.at(i, j, k);
     V5<T> L = to_frame<D>(ld(SL, c.nc, q));
     V5<T> R = to_frame<D>(ld(SR, c.nc, q + s));
-    st(c.F[D], c.nc, q, from_frame<D>(riemann<RS>(L, R, ph, fails)));
+    st(c.F[D], c.nc, q, from_frame<D>(plain_solve<RS>(L, R, ph, c.roe_fb_exact, fails)));
   });
   return fb;
 }
@@ -144,6 +169,7 @@ __global__ void __launch_bounds__(256) plain_kernel(PlainArgs<T> a) {
   PlainCtx<T> c;
   c.N = N;
   c.nc = nc;
+  c.roe_fb_exact = a.roe_fb_exact;
   T* base = a.ws + (long)blockIdx.x * a.ws_stride;
   c.W = base;
   for (int d = 0; d < 3; ++d) {
@@ -301,7 +327,7 @@ hipError_t launch_plain_t(const PlainArgs<T>& a, int scheme, int recon, int riem
   dim3 blk(256), grd(grid);
 #define PL(S, P, R) \
   if (scheme == S && recon == P && riemann == R) { plain_kernel<T, S, P == 1, R><<<grd, blk, 0, st>>>(a); return hipGetLastError(); }
-#define PLR(S, P) PL(S, P, 0) PL(S, P, 1) PL(S, P, 2)
+#define PLR(S, P) PL(S, P, 0) PL(S, P, 1) PL(S, P, 2) PL(S, P, 3)
   PLR(0, 0) PLR(0, 1) PLR(1, 0) PLR(1, 1) PLR(2, 0) PLR(2, 1)
 #undef PLR
 #undef PL

@@ -17,9 +17,10 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhydro.so
 
 MHM, VL, CTU = 0, 1, 2
 PLM, PPM = 0, 1
-ROE, HLLC, HLLE = 0, 1, 2
+ROE, HLLC, HLLE, EXACT = 0, 1, 2, 3
 GMINMOD, VANLEER, VANALBADA, HYBRID = 0, 1, 2, 3
-F64, CHAR, FLUX_MID, PLAIN, ROE_FB_HLLC, BOX_GROUPED, BOX_SEGS = 0x01, 0x02, 0x04, 0x08, 0x10, 0x20, 0x40
+F64, CHAR, FLUX_MID, PLAIN, ROE_FB_HLLC, BOX_GROUPED, BOX_SEGS, ROE_FB_EXACT = 0x01, 0x02, 0x04, 0x08, 0x10, 0x20, \
+    0x40, 0x80
 
 EXPORTS = (
     "hydro_ghost_width", "hydro_solve_groups", "hydro_cfl_dt", "hydro_conserved_sums", "hydro_cfl_dt_sums",
@@ -150,8 +151,9 @@ def ghost_width(scheme: int, recon: int) -> int:
 
 
 def solve_groups(inp, out, flux=None, *, dt, dh, gamma, scheme, recon, riemann, limiter=VANLEER, char=False,
-                 plain=False, flux_mid=False, roe_fb_hllc=False, stream=None):
-    """One step of n patch groups: inp [n,5,N,N,N] -> out [n,5,16,16,16]."""
+                 plain=False, flux_mid=False, roe_fb_hllc=False, roe_fb_exact=False, stream=None):
+    """One step of n patch groups: inp [n,5,N,N,N] -> out [n,5,16,16,16].
+    riemann=EXACT and roe_fb_exact run on the plain path."""
     n = inp.shape[0]
     N = 16 + 2 * ghost_width(scheme, recon)
     _require(inp, "inp", (n, 5, N, N, N))
@@ -159,7 +161,7 @@ def solve_groups(inp, out, flux=None, *, dt, dh, gamma, scheme, recon, riemann, 
     if flux is not None:
         _require(flux, "flux", (n, 3, 3 if flux_mid else 2, 5, 16, 16), inp.dtype)
     flags = _dtype_flag(inp) | (CHAR if char else 0) | (PLAIN if plain else 0) | (FLUX_MID if flux_mid else 0) \
-        | (ROE_FB_HLLC if roe_fb_hllc else 0)
+        | (ROE_FB_HLLC if roe_fb_hllc else 0) | (ROE_FB_EXACT if roe_fb_exact else 0)
     _check("hydro_solve_groups", lib().hydro_solve_groups(
         _ptr(inp), _ptr(out), _ptr(flux), n, float(dt), float(dh), float(gamma), scheme, recon, riemann, limiter,
         flags, _stream(stream)))

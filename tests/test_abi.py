@@ -61,8 +61,15 @@ def test_argument_validation(L):
     assert _solve(L, gamma=1.0) == EINVAL
     assert _solve(L, scheme=3) == EINVAL
     assert _solve(L, recon=2) == EINVAL
-    assert _solve(L, riemann=3) == EUNSUP  # exact solver: oracle only
+    assert _solve(L, riemann=3) not in (EINVAL, EUNSUP)  # exact solver: accepted (plain path)
+    assert _solve(L, riemann=0, flags=0x80) not in (EINVAL, EUNSUP)  # Roe -> exact fallback: accepted
     assert _solve(L, riemann=4) == EINVAL
+    # The fused-only box step has no exact solver and no exact fallback.
+    P = ctypes.c_void_p
+    step = lambda rs, fl: L.hydro_step_box(P(0x1000), P(0x100000000), None, 32, 32, 32, P(0x2000), 1.0, 1.0 / 32,
+                                           1.4, 2, 1, rs, 1, fl, None)
+    assert step(3, 0) == EUNSUP
+    assert step(0, 0x80) == EUNSUP
     assert _solve(L, limiter=4) == EINVAL
     assert _solve(L, flags=0x100) == EINVAL
     assert _solve(L, inp=0, out=0x2000) == EINVAL

@@ -450,3 +450,56 @@ def test_amr_cycle_conserves_on_gpu(H):
     t0 = box.reshape(5, -1).sum(1)
     t1 = W.groups_to_box(got, n, n, n).reshape(5, -1).sum(1)
     assert np.abs(t1 - t0).max() <= 1e-13 * np.abs(t0).max()
+
+
+@pytest.mark.parametrize("scheme,recon,char", [(0, 0, False), (0, 1, True), (1, 0, True), (1, 1, False),
+                                               (2, 0, False), (2, 1, True)])
+def test_fp64_exact_solver_matches_oracle(H, scheme, recon, char):
+    """The exact Riemann solver (plain path) on a blast field with shocks and
+    rarefactions against the oracle's exact solver: Newton to a relative
+    change below 1e-15 on both sides, so the FP64 results agree to 1e-12."""
+    gamma = 1.4
+    box = W.lognormal_blast_box(32, gamma=gamma, seed=23, radius_cells=3)
+    g, G = _groups(box, scheme, recon)
+    G = G[:3]
+    dt = O.cfl_dt(box, 1 / 32, gamma, 0.5 if scheme == 2 else 0.3)
+    flags = (O.F_CHAR if char else 0) | O.F_FLUX_MID
+    ref, rflux = O.solve_groups(G, g, dt, 1 / 32, gamma, scheme, recon, 3, 1, flags, want_flux=True)
+    out, flux = _run(H, G, g, torch.float64, dt, 1 / 32, gamma, scheme, recon, 3, 1, char, False, flux_mid=True)
+    assert scaled_max_err(out, ref) <= 1e-12
+    assert scaled_max_err(flux, rflux) <= 1e-12
+
+
+def test_fp32_exact_solver_smooth(H):
+    """FP32 exact solver (Newton to 1e-6) within 1e-5 of the FP64 oracle."""
+    gamma = 1.4
+    box = random_smooth_box(32, gamma, 11, amp=0.3)
+    for scheme, recon in ((2, 1), (0, 0)):
+        g = O.ghost_width(scheme, recon)
+        G = O.fill_ghosts_periodic(box, g).astype(np.float32).astype(np.float64)[:2]
+        ref, _ = O.solve_groups(G, g, 4e-3, 1 / 32, gamma, scheme, recon, 3, 1, O.F_CHAR)
+        out, _ = _run(H, G, g, torch.float32, 4e-3, 1 / 32, gamma, scheme, recon, 3, 1, True, False, False)
+        l1, linf = rel_errors(out, ref)
+        assert l1.max() <= 1e-5 and linf.max() <= 1e-5, (l1, linf)
+
+
+def test_roe_exact_fallback(H):
+    """Strong double rarefaction: with the exact fallback every face where
+    the Roe linearization fails takes the exact flux (plain path), matching
+    the oracle with the same fallback; the failures are still counted."""
+    gamma = 1.4
+    x = (np.arange(32) + 0.5) / 32
+    u = np.where(x < 0.5, -2.0, 2.0)[None, None, :] * np.ones((32, 32, 1))
+    box = W.primitive_to_conserved(np.ones_like(u), u, 0 * u, 0 * u, 0.4 * np.ones_like(u), gamma)
+    g, G = _groups(box, 2, 0)
+    ref_exact, _ = O.solve_groups(G, g, 2e-3, 1 / 32, gamma, 2, 0, 0, 1, O.F_ROE_FB_EXACT)
+    ref_hlle, _ = O.solve_groups(G, g, 2e-3, 1 / 32, gamma, 2, 0, 0, 1, 0)
+    assert scaled_max_err(ref_exact, ref_hlle) > 1e-8  # the fallback flux matters here
+    inp = _dev(G, torch.float64)
+    out = torch.empty((G.shape[0], 5, 16, 16, 16), dtype=torch.float64, device="cuda")
+    H.get_diag(reset=True)
+    H.solve_groups(inp, out, None, dt=2e-3, dh=1 / 32, gamma=gamma, scheme=2, recon=0, riemann=0, limiter=1,
+                   roe_fb_exact=True)
+    d = H.get_diag(reset=True)
+    assert scaled_max_err(out.cpu().numpy(), ref_exact) <= 1e-12
+    assert d["roe_fallbacks"] >= 1

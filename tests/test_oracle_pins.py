@@ -167,6 +167,13 @@ def test_roe_fails_on_strong_double_rarefaction(oracle):
     np.testing.assert_array_equal(oracle.riemann_flux(L, R, 0, 1.4, 0), oracle.riemann_flux(L, R, 0, 1.4, 2))
     np.testing.assert_array_equal(oracle.riemann_flux(L, R, 0, 1.4, 0, 0x10),
                                   oracle.riemann_flux(L, R, 0, 1.4, 1))
+    # ... or, with the exact fallback, the exact flux; where Roe succeeds the
+    # flag changes nothing.
+    np.testing.assert_array_equal(oracle.riemann_flux(L, R, 0, 1.4, 0, oracle.F_ROE_FB_EXACT),
+                                  oracle.riemann_flux(L, R, 0, 1.4, 3))
+    ok_l, ok_r = [1.0, 0, 0, 0, 1.0], [0.125, 0, 0, 0, 0.1]
+    np.testing.assert_array_equal(oracle.riemann_flux(ok_l, ok_r, 0, 1.4, 0, oracle.F_ROE_FB_EXACT),
+                                  oracle.riemann_flux(ok_l, ok_r, 0, 1.4, 0))
 
 
 def test_hlle_first_order_update_is_positive(oracle):
