@@ -501,6 +501,17 @@ def main():
         plain = {"path": "plain per-group FP64 (one workgroup per group, global temporaries)",
                  "ms_per_solve": round(pms, 3), "cell_updates_per_s": cells / (pms * 1e-3),
                  "speedup_of_fused_solve": round(pms / kern_avg, 2)}
+        # The exact Riemann solver (plain path only) on the same input, FP64.
+        H.get_diag(reset=True)
+        pe[0].record(stream)
+        H.solve_groups(gh64, out64, None, dt=dt0, dh=dh, gamma=gamma, scheme=H.CTU, recon=H.PPM, riemann=H.EXACT,
+                       limiter=H.VANLEER, char=True)
+        pe[1].record(stream)
+        torch.cuda.synchronize()
+        ems = pe[0].elapsed_time(pe[1])
+        plain["exact_solver"] = {"ms_per_solve": round(ems, 3), "cell_updates_per_s": cells / (ems * 1e-3),
+                                 "vacuum_or_unconverged_faces": H.get_diag(reset=True)["roe_fallbacks"],
+                                 "finite": bool(torch.isfinite(out64).all().item())}
         del gh64, out64
 
     cpu = None
