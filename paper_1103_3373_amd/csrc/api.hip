@@ -591,7 +591,7 @@ int hydro_amr_correct(void* coarse, int n, const void* coarse_flux, const void* 
                       void* stream) {
   g_err[0] = 0;
   if (n <= 0 || n % 16 || n > 8192) return fail(HYDRO_EINVAL, "coarse box size must be a positive multiple of 16");
-  if (n_fine < 0) return fail(HYDRO_EINVAL, "n_fine < 0");
+  if (n_fine < 0 || n_fine > (1 << 28)) return fail(HYDRO_EINVAL, "n_fine must be in [0, 2^28]");
   if (!(dt > 0.0) || !isfinite(dt) || !(dh > 0.0) || !isfinite(dh))
     return fail(HYDRO_EINVAL, "dt and dh must be positive and finite");
   if (flags & ~HYDRO_F64) return fail(HYDRO_EINVAL, "only HYDRO_F64 is accepted");

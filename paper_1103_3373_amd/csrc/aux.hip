@@ -409,76 +409,89 @@ __device__ __forceinline__ int fine_owner(const int* fmap, int nf, int ngf, int 
   return (o >= 0 && o < nf) ? o : -1;
 }
 
-// Refluxing, one thread per coarse cell.  An uncovered cell next to a
-// covered one across a face replaces the coarse flux of that face (stored
-// by the coarse step on the patch faces: group faces -, + and the mid plane)
-// by the mean of the four fine fluxes on it: U -= dt/dh (Ff - Fc) when the
-// fine cell lies on its + side, += on its - side, in the order x, y, z and
-// -, +.  No contraction: the same FP64 expression as a plain evaluation.
+// Refluxing.  An uncovered coarse cell next to a covered one across a face
+// replaces the coarse flux of that face (stored by the coarse step on the
+// patch faces: group faces -, + and the mid plane) by the mean of the four
+// fine fluxes on it: U -= dt/dh (Ff - Fc) when the fine cell lies on its +
+// side, += on its - side, in the order x, y, z and -, +.  No contraction:
+// the same FP64 expression as a plain evaluation.
+//
+// One 64-thread workgroup per face of a fine group, one thread per coarse
+// cell just outside that face (8 x 8).  A cell next to several refined
+// patches is visited from several faces; only the face of its first covered
+// neighbour in the order above processes it, applying all of its
+// corrections in that order, so every cell is written by one thread.
 template <typename T>
-__global__ void __launch_bounds__(256) reflux_kernel(T* __restrict__ U, int n, const T* __restrict__ cflux,
-                                                     const int* __restrict__ fmap, int nf,
-                                                     const T* __restrict__ fflux, const int4* __restrict__ flayout,
-                                                     double dtdh) {
+__global__ void __launch_bounds__(64) reflux_kernel(T* __restrict__ U, int n, const T* __restrict__ cflux,
+                                                    const int* __restrict__ fmap, int nf, const T* __restrict__ fflux,
+                                                    const int4* __restrict__ flayout, double dtdh) {
 #pragma clang fp contract(off)
-  // 16 workgroups of 256 threads per coarse group: the group and its
-  // coordinates are uniform over a workgroup.
-  const int ng = n >> 4, ngf = n >> 3;
-  const long long G = blockIdx.x >> 4;
-  const int l = (int)(((blockIdx.x & 15) << 8) | threadIdx.x);
-  const int lx = l & 15, ly = (l >> 4) & 15, lz = l >> 8;
-  const int gx = (int)(G % ng), gy = (int)((G / ng) % ng), gz = (int)(G / ((long long)ng * ng));
-  // Fine groups cover whole 8^3 coarse patches, so only cells on a patch
-  // face (local index 0, 7, 8 or 15 along some axis) can border one.
-  const int loc[3] = {lx, ly, lz};
-  auto edge = [](int q) { return (q & 7) == 0 || (q & 7) == 7; };
-  if (!edge(lx) && !edge(ly) && !edge(lz)) return;
-  const int c[3] = {gx * 16 + lx, gy * 16 + ly, gz * 16 + lz};
-  if (fine_owner(fmap, nf, ngf, c[0], c[1], c[2]) >= 0) return;
+  const int F0 = blockIdx.x / 6, face = blockIdx.x % 6;
+  const int dF = face >> 1, sF = (face & 1) ? 1 : -1;  // the fine group's face: axis and side
+  const int4 o0 = flayout[F0];
+  const int nfine = 2 * n, ng = n >> 4, ngf = n >> 3;
+  if (o0.y < 0 || o0.z < 0 || o0.w < 0 || o0.y >= nfine || o0.z >= nfine || o0.w >= nfine ||
+      ((o0.y | o0.z | o0.w) & 15))
+    return;
+  const int c0[3] = {o0.y >> 1, o0.z >> 1, o0.w >> 1};
+  if (fine_owner(fmap, nf, ngf, c0[0], c0[1], c0[2]) != F0) return;
+  // The coarse cell a outside this face; from a, the refined patch lies on
+  // side -sF along dF.
+  const int e1 = dF == 0 ? 1 : 0, e2 = dF == 2 ? 1 : 2;
+  int c[3];
+  c[dF] = sF < 0 ? c0[dF] - 1 : c0[dF] + 8;
+  c[dF] += c[dF] < 0 ? n : 0;
+  c[dF] -= c[dF] >= n ? n : 0;
+  c[e1] = c0[e1] + (threadIdx.x & 7);
+  c[e2] = c0[e2] + (threadIdx.x >> 3);
+  if (fine_owner(fmap, nf, ngf, c[0], c[1], c[2]) >= 0) return;  // covered: restriction sets it
+  int owners[6];
+  int first = -1;
+  for (int q = 0; q < 6; ++q) {
+    const int d = q >> 1, side = (q & 1) ? 1 : -1;
+    int b[3] = {c[0], c[1], c[2]};
+    b[d] += side;
+    b[d] += b[d] < 0 ? n : 0;
+    b[d] -= b[d] >= n ? n : 0;
+    owners[q] = fine_owner(fmap, nf, ngf, b[0], b[1], b[2]);
+    if (owners[q] >= 0 && first < 0) first = q;
+  }
+  if (first != dF * 2 + (sF < 0 ? 1 : 0)) return;  // another face processes this cell
+  const long long G = ((long long)(c[2] >> 4) * ng + (c[1] >> 4)) * ng + (c[0] >> 4);
+  const int l = ((c[2] & 15) * 16 + (c[1] & 15)) * 16 + (c[0] & 15);
+  const int loc[3] = {c[0] & 15, c[1] & 15, c[2] & 15};
   double u[5];
-  bool touched = false;  // U is read at the first correction only
-  for (int d = 0; d < 3; ++d) {
+#pragma unroll
+  for (int v = 0; v < 5; ++v) u[v] = (double)U[(G * 5 + v) * 4096 + l];
+  for (int q = 0; q < 6; ++q) {
+    const int F = owners[q];
+    if (F < 0) continue;
+    const int d = q >> 1, side = (q & 1) ? 1 : -1;
     // transverse coordinates (slow, fast) of a d-face: x (z, y), y (z, x), z (y, x)
     const int ts = d == 2 ? 1 : 2, tf = d == 0 ? 1 : 0;
-    for (int side = -1; side <= 1; side += 2) {
-      if ((loc[d] & 7) != (side > 0 ? 7 : 0)) continue;  // not on a patch face on this side
-      int b[3] = {c[0], c[1], c[2]};
-      b[d] += side;
-      b[d] += b[d] < 0 ? n : 0;
-      b[d] -= b[d] >= n ? n : 0;
-      const int F = fine_owner(fmap, nf, ngf, b[0], b[1], b[2]);
-      if (F < 0) continue;
-      const int slot = side > 0 ? (loc[d] == 15 ? 1 : (loc[d] == 7 ? 2 : -1)) : (loc[d] == 0 ? 0 : (loc[d] == 8 ? 2 : -1));
-      if (slot < 0) continue;  // cannot happen: fine groups cover whole coarse patches
-      const int4 o = flayout[F];
-      const int fo[3] = {o.y, o.z, o.w};
-      const int fs0 = 2 * (c[ts] - (fo[ts] >> 1)), ff0 = 2 * (c[tf] - (fo[tf] >> 1));
-      if (fs0 < 0 || fs0 > 14 || ff0 < 0 || ff0 > 14) continue;  // layout disagrees with the map
-      const int fslot = side > 0 ? 0 : 1;
-      const double sg = side > 0 ? -1.0 : 1.0;
-      if (!touched) {
+    const int slot = side > 0 ? (loc[d] == 15 ? 1 : (loc[d] == 7 ? 2 : -1)) : (loc[d] == 0 ? 0 : (loc[d] == 8 ? 2 : -1));
+    if (slot < 0) continue;  // cannot happen: fine groups cover whole coarse patches
+    const int4 o = flayout[F];
+    const int fo[3] = {o.y, o.z, o.w};
+    const int fs0 = 2 * (c[ts] - (fo[ts] >> 1)), ff0 = 2 * (c[tf] - (fo[tf] >> 1));
+    if (fs0 < 0 || fs0 > 14 || ff0 < 0 || ff0 > 14) continue;  // layout disagrees with the map
+    const int fslot = side > 0 ? 0 : 1;  // F's face towards this cell
+    const double sg = side > 0 ? -1.0 : 1.0;
 #pragma unroll
-        for (int v = 0; v < 5; ++v) u[v] = (double)U[(G * 5 + v) * 4096 + l];
-        touched = true;
-      }
-#pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        const double Fc = (double)cflux[((((G * 3 + d) * 3 + slot) * 5 + v) * 16 + loc[ts]) * 16 + loc[tf]];
-        const T* f = fflux + ((((long long)F * 3 + d) * 2 + fslot) * 5 + v) * 256;
-        double Ff = 0.0;
-        Ff += (double)f[fs0 * 16 + ff0];
-        Ff += (double)f[fs0 * 16 + ff0 + 1];
-        Ff += (double)f[(fs0 + 1) * 16 + ff0];
-        Ff += (double)f[(fs0 + 1) * 16 + ff0 + 1];
-        Ff *= 0.25;
-        u[v] += sg * dtdh * (Ff - Fc);
-      }
+    for (int v = 0; v < 5; ++v) {
+      const double Fc = (double)cflux[((((G * 3 + d) * 3 + slot) * 5 + v) * 16 + loc[ts]) * 16 + loc[tf]];
+      const T* f = fflux + ((((long long)F * 3 + d) * 2 + fslot) * 5 + v) * 256;
+      double Ff = 0.0;
+      Ff += (double)f[fs0 * 16 + ff0];
+      Ff += (double)f[fs0 * 16 + ff0 + 1];
+      Ff += (double)f[(fs0 + 1) * 16 + ff0];
+      Ff += (double)f[(fs0 + 1) * 16 + ff0 + 1];
+      Ff *= 0.25;
+      u[v] += sg * dtdh * (Ff - Fc);
     }
   }
-  if (touched) {
 #pragma unroll
-    for (int v = 0; v < 5; ++v) U[(G * 5 + v) * 4096 + l] = (T)u[v];
-  }
+  for (int v = 0; v < 5; ++v) U[(G * 5 + v) * 4096 + l] = (T)u[v];
 }
 
 // Restriction: one workgroup per fine group, one thread per covered coarse
@@ -517,11 +530,11 @@ __global__ void __launch_bounds__(512) restrict_kernel(T* __restrict__ U, int n,
 template <typename T>
 hipError_t launch_amr_correct(T* U, int n, const T* cflux, const T* fine, const int* flayout, int nf,
                               const int* fmap, const T* fflux, double dtdh, hipStream_t st) {
-  const long long blocks = (long long)(n / 16) * (n / 16) * (n / 16) * 16;  // n <= 8192: below 2^31
-  reflux_kernel<T><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(U, n, cflux, fmap, nf, fflux, (const int4*)flayout,
-                                                                  dtdh);
+  if (nf == 0) return hipSuccess;
+  reflux_kernel<T><<<dim3((unsigned)(6 * (long long)nf)), dim3(64), 0, st>>>(U, n, cflux, fmap, nf, fflux,
+                                                                             (const int4*)flayout, dtdh);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || nf == 0) return e;
+  if (e != hipSuccess) return e;
   restrict_kernel<T><<<dim3((unsigned)nf), dim3(512), 0, st>>>(U, n, fine, (const int4*)flayout, fmap, nf);
   return hipGetLastError();
 }
