@@ -6,6 +6,8 @@
 //    single-block finish, dt = cfl * dh / max (max is order-free, so the
 //    result is deterministic and equals a serial evaluation bit for bit);
 //  * FP64 conserved sums with a fixed two-level reduction order.
+#include <limits.h>
+
 #include "hydro_internal.h"
 
 namespace hy {
@@ -267,9 +269,14 @@ hipError_t launch_group_map(const int* layout, int n_groups, int ng0, int n_leve
 // alpha_l coarse1 at the four coarse points of a layer, interpolated in x
 // and y and then in z between the two layers that bracket the cell; a
 // thread keeps both layers' values and recomputes them only when the pair
-// moves.  No contraction: a plain FP64 evaluation of that expression.  Map
-// entries outside [0, n_groups) count as empty, and levels are clamped into
-// range, so every access stays inside the arrays whatever the layout holds.
+// moves.  When the coarse points that the group's padded region touches fit
+// in kFoot^3 (levels at least about 4x finer than the coarse field), the
+// workgroup first blends them once into LDS and the columns interpolate
+// from there; otherwise every column blends from global memory.  Both give
+// the same values.  No contraction: a plain FP64 evaluation of that
+// expression.  Map entries outside [0, n_groups) count as empty, and levels
+// are clamped into range, so every access stays inside the arrays whatever
+// the layout holds.
 template <typename T>
 struct AmrArgs {
   const T* fine;       // [n][5][16][16][16]
@@ -282,17 +289,19 @@ struct AmrArgs {
   double alpha[8];
 };
 
+constexpr int kFoot = 8;  // coarse points per axis staged in LDS
+
 template <typename T, int G>
 __global__ void __launch_bounds__(interp_threads<G>()) fill_amr_group_kernel(AmrArgs<T> a) {
 #pragma clang fp contract(off)
   constexpr int N = 16 + 2 * G;
   constexpr long long nc = (long long)N * N * N;
+  __shared__ double sB[5][kFoot * kFoot * kFoot];  // blended coarse footprint, [n][z][y][x]
   const int cn = a.cn;
   const long long cc = (long long)cn * cn * cn;
   const long long grp = blockIdx.x;
   const int4 L = a.layout[grp];
   const int r = threadIdx.x;
-  if (r >= N * N) return;  // no barrier below
   const int lev = L.x < 0 ? 0 : (L.x >= a.n_levels ? a.n_levels - 1 : L.x);
   const long long ng = (long long)a.ng0 << lev;
   const int nl = (int)(16 * ng);
@@ -303,17 +312,50 @@ __global__ void __launch_bounds__(interp_threads<G>()) fill_amr_group_kernel(Amr
   }
   const double dh = 1.0 / (double)nl;
   const double al = a.alpha[lev];
+  // Coarse-index coordinate of the centre of padded-region cell c (-G .. 15+G)
+  // along an axis whose group origin is o.
+  auto coord = [&](int o, int c) -> double { return (((double)o + c) + 0.5) * dh * cn - 0.5; };
+  // Footprint: unwrapped coarse indices lo .. lo + W - 1 per axis.
+  const int lox = (int)floor(coord(L.y, -G)), loy = (int)floor(coord(L.z, -G)), loz = (int)floor(coord(L.w, -G));
+  const int wx = (int)floor(coord(L.y, 15 + G)) + 2 - lox, wy = (int)floor(coord(L.z, 15 + G)) + 2 - loy,
+            wz = (int)floor(coord(L.w, 15 + G)) + 2 - loz;
+  // Uniform over the workgroup.  Origins outside the level take the direct
+  // path, whose indices all wrap.
+  const bool staged = L.y >= 0 && L.y < nl && L.z >= 0 && L.z < nl && L.w >= 0 && L.w < nl && wx <= kFoot &&
+                      wy <= kFoot && wz <= kFoot;
+  if (staged) {
+    for (int q = r; q < 5 * kFoot * kFoot * kFoot; q += blockDim.x) {
+      const int n = q / (kFoot * kFoot * kFoot), p = q % (kFoot * kFoot * kFoot);
+      const int ix = p % kFoot, iy = (p / kFoot) % kFoot, iz = p / (kFoot * kFoot);
+      if (ix < wx && iy < wy && iz < wz) {
+        const long long g = (long long)n * cc +
+                            ((long long)wrap_index((long long)loz + iz, cn) * cn + wrap_index((long long)loy + iy, cn)) *
+                                cn +
+                            wrap_index((long long)lox + ix, cn);
+        sB[n][p] = (1.0 - al) * (double)a.c0[g] + al * (double)a.c1[g];
+      }
+    }
+    __syncthreads();
+  }
+  if (r >= N * N) return;  // no barrier below
   const int ci = r % N - G, cj = r / N - G;
   const bool in_xy = ci >= 0 && ci < 16 && cj >= 0 && cj < 16;
   const int px = wrap_index((long long)L.y + ci, nl), py = wrap_index((long long)L.z + cj, nl);
-  const double X = (((double)L.y + ci) + 0.5) * dh * cn - 0.5;
-  const double Y = (((double)L.z + cj) + 0.5) * dh * cn - 0.5;
+  const double X = coord(L.y, ci), Y = coord(L.z, cj);
   const double fx0 = floor(X), fy0 = floor(Y);
   const double ax = X - fx0, ay = Y - fy0;
   const int x0 = wrap_index((long long)fx0, cn), y0 = wrap_index((long long)fy0, cn);
   const int x1 = x0 + 1 == cn ? 0 : x0 + 1, y1 = y0 + 1 == cn ? 0 : y0 + 1;
-  auto layer = [&](int z, int n) -> double {
-    const long long base = (long long)n * cc + (long long)z * cn * cn;
+  const int sx = (int)fx0 - lox, sy = (int)fy0 - loy;  // staged footprint indices
+  // x-y interpolation of layer z (unwrapped coarse index) of variable n.
+  auto layer = [&](int zu, int n) -> double {
+    if (staged) {
+      const double* f = sB[n] + (zu - loz) * kFoot * kFoot;
+      const double v00 = (1.0 - ax) * f[sy * kFoot + sx] + ax * f[sy * kFoot + sx + 1];
+      const double v01 = (1.0 - ax) * f[(sy + 1) * kFoot + sx] + ax * f[(sy + 1) * kFoot + sx + 1];
+      return (1.0 - ay) * v00 + ay * v01;
+    }
+    const long long base = (long long)n * cc + (long long)wrap_index(zu, cn) * cn * cn;
     const T* f0 = a.c0 + base;
     const T* f1 = a.c1 + base;
     auto b = [&](int q) -> double { return (1.0 - al) * (double)f0[q] + al * (double)f1[q]; };
@@ -323,8 +365,22 @@ __global__ void __launch_bounds__(interp_threads<G>()) fill_amr_group_kernel(Amr
   };
   const T* own = a.fine + grp * 5 * 4096;
   T* o = a.out + grp * 5 * nc + r;
+  // The column meets three group positions along z (below, its own, above;
+  // G < 16): their map entries are read once, before the march.
+  int owner3[3];
+  {
+    const long long gzc = wrap_index((long long)L.w, nl) >> 4;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      long long gz = gzc + t - 1;
+      gz += gz < 0 ? ng : 0;
+      gz -= gz >= ng ? ng : 0;
+      const int ow = a.map[moff + (gz * ng + (py >> 4)) * ng + (px >> 4)];
+      owner3[t] = (ow >= 0 && ow < a.n_groups) ? ow : -1;
+    }
+  }
   double v0[5], v1[5];
-  int zc = -1;
+  long long zc = LLONG_MIN;  // unwrapped coarse layer of v0 (none yet)
   for (int k = 0; k < N; ++k) {
     const int ck = k - G;
     T val[5];
@@ -333,22 +389,22 @@ __global__ void __launch_bounds__(interp_threads<G>()) fill_amr_group_kernel(Amr
       for (int n = 0; n < 5; ++n) val[n] = own[n * 4096 + (ck * 16 + cj) * 16 + ci];
     } else {
       const int pz = wrap_index((long long)L.w + ck, nl);
-      const int owner = a.map[moff + ((long long)(pz >> 4) * ng + (py >> 4)) * ng + (px >> 4)];
-      if (owner >= 0 && owner < a.n_groups) {
+      const int owner = owner3[ck < 0 ? 0 : (ck < 16 ? 1 : 2)];
+      if (owner >= 0) {
         const T* s = a.fine + (long long)owner * 5 * 4096 + ((pz & 15) * 16 + (py & 15)) * 16 + (px & 15);
 #pragma unroll
         for (int n = 0; n < 5; ++n) val[n] = s[n * 4096];
       } else {
-        const double Z = (((double)L.w + ck) + 0.5) * dh * cn - 0.5;
+        const double Z = coord(L.w, ck);
         const double fz0 = floor(Z);
         const double az = Z - fz0;
-        const int z0 = wrap_index((long long)fz0, cn), z1 = z0 + 1 == cn ? 0 : z0 + 1;
+        const long long z0 = (long long)fz0;
         if (z0 != zc) {
-          const bool shift = zc >= 0 && z0 == (zc + 1 == cn ? 0 : zc + 1);
+          const bool shift = z0 == zc + 1;
 #pragma unroll
           for (int n = 0; n < 5; ++n) {
-            v0[n] = shift ? v1[n] : layer(z0, n);
-            v1[n] = layer(z1, n);
+            v0[n] = shift ? v1[n] : layer((int)z0, n);
+            v1[n] = layer((int)z0 + 1, n);
           }
           zc = z0;
         }

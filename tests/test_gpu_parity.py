@@ -314,13 +314,16 @@ def test_group_map_matches_numpy(H):
 
 @pytest.mark.parametrize("g", [2, 3, 4])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_amr_fill_matches_oracle(H, g, dtype):
+@pytest.mark.parametrize("cn", [8, 64])
+def test_amr_fill_matches_oracle(H, g, dtype, cn):
     """Preparation with same-level neighbours and time-blended coarse ghosts
     on three sparse levels: copied cells bit for bit, interpolated cells to
     FP64 rounding (the oracle sums eight weighted corners, the kernel
-    interpolates axis by axis) or to FP32 rounding of the result."""
+    interpolates axis by axis) or to FP32 rounding of the result.  With the
+    8^3 coarse field every group's coarse footprint is staged in LDS; the
+    64^3 one is too fine for that, so every column reads it directly."""
     ng0, alpha = 2, [0.0, 0.25, 0.625]
-    lay, fine, c0, c1 = _amr_case(ng0, (4, 12, 40), 8, 31)
+    lay, fine, c0, c1 = _amr_case(ng0, (4, 12, 40), cn, 31)
     if dtype == torch.float32:
         fine, c0, c1 = (a.astype(np.float32).astype(np.float64) for a in (fine, c0, c1))
     want = O.fill_groups_amr(fine, lay, ng0, alpha, c0, c1, g)
