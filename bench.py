@@ -66,7 +66,7 @@ def parse():
     p.add_argument("--extra-reps", type=int, default=10,
                    help="launches per side measurement (groups API, other schemes, copy); 0 skips them")
     p.add_argument("--no-autotune", action="store_true", help="skip the launch-shape autotuner")
-    p.add_argument("--graph-replays", type=int, default=10, help="replays of a captured two-step HIP graph")
+    p.add_argument("--graph-replays", type=int, default=10, help="replays of a captured ten-step HIP graph")
     p.add_argument("--serve", action="store_true",
                    help="run the serving workload instead (Poisson arrivals, continuous batching)")
     p.add_argument("--amr", action="store_true",
@@ -449,14 +449,16 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     per_step = np.array([step_ev[i].elapsed_time(step_ev[i + 1]) for i in range(args.steps)])  # ms
-    # The same steps replayed from a captured HIP graph (two steps per graph).
+    # The same steps replayed from a captured HIP graph (ten steps per graph,
+    # an even count so the double buffers end where they started).
     graph_ms = None
+    graph_steps = 10
     if args.graph_replays > 0:
         side = torch.cuda.Stream()
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph, stream=side):
-            step(0, False)
-            step(1, False)
+            for i in range(graph_steps):
+                step(i, False)
         torch.cuda.synchronize()
         graph.replay()
         torch.cuda.synchronize()
@@ -466,7 +468,7 @@ def main():
             graph.replay()
         g1.record(stream)
         torch.cuda.synchronize()
-        graph_ms = g0.elapsed_time(g1) / (2 * args.graph_replays)
+        graph_ms = g0.elapsed_time(g1) / (graph_steps * args.graph_replays)
     total_ms = step_ev[0].elapsed_time(step_ev[-1])
     kern_ms = np.array([a.elapsed_time(b) for a, b in k_ev])
     ms_per_step = total_ms / args.steps
