@@ -2,8 +2,8 @@
 marshalling only -- every step of the solver runs in the HIP library).
 
 Device buffers are torch tensors on a HIP device; the current torch stream is
-passed to every call.  The library must be built (``__graft_entry__.build()``
-or ``python -m paper_1103_3373_amd.build``); if ``libhydro.so`` is missing or
+passed to every call.  The library must be built
+(``python -m paper_1103_3373_amd.build``); if ``libhydro.so`` is missing or
 cannot be loaded, every call raises -- there is no CPU fallback.
 """
 from __future__ import annotations
@@ -62,7 +62,7 @@ def lib() -> ctypes.CDLL:
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing (run __graft_entry__.build())")
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing (run python -m paper_1103_3373_amd.build)")
     L = ctypes.CDLL(LIB_PATH)
     P, i, d, ll = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_longlong
     L.hydro_ghost_width.argtypes = [i, i]
