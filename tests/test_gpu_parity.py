@@ -312,7 +312,7 @@ def test_group_map_matches_numpy(H):
     np.testing.assert_array_equal(got, want)
 
 
-@pytest.mark.parametrize("g", [2, 3, 4])
+@pytest.mark.parametrize("g", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("cn", [8, 64])
 def test_amr_fill_matches_oracle(H, g, dtype, cn):
@@ -506,3 +506,24 @@ def test_roe_exact_fallback(H):
     d = H.get_diag(reset=True)
     assert scaled_max_err(out.cpu().numpy(), ref_exact) <= 1e-12
     assert d["roe_fallbacks"] >= 1
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_accumulate(H, dtype):
+    """acc += w x evaluated in FP64 and rounded to the buffer type, also with
+    acc and x the same buffer; the sub-step average of two flux arrays."""
+    rng = np.random.default_rng(61)
+    a = rng.standard_normal(1000)
+    x = rng.standard_normal(1000)
+    if dtype == torch.float32:
+        a, x = a.astype(np.float32).astype(np.float64), x.astype(np.float32).astype(np.float64)
+    acc = _dev(a, dtype)
+    H.accumulate(acc, _dev(x, dtype), 0.375)
+    want = a + 0.375 * x
+    got = acc.cpu().numpy().astype(np.float64)
+    if dtype == torch.float64:
+        np.testing.assert_array_equal(got, want)
+    else:
+        np.testing.assert_array_equal(got, want.astype(np.float32).astype(np.float64))
+    H.accumulate(acc, acc, -0.5)
+    np.testing.assert_allclose(acc.cpu().numpy().astype(np.float64), 0.5 * got, rtol=1e-7 if dtype == torch.float32 else 0)
