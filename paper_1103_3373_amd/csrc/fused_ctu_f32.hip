@@ -1,7 +1,11 @@
-// Instantiations of the fused CTU kernel for float.
+// Instantiations of the fused CTU kernel for float with the HLLC and HLLE
+// solvers (the Roe instantiations live in fused_ctu_f32_roe.hip, which is
+// compiled with other scheduler options).
 #include "fused_ctu.hpp"
 
 namespace hy {
+
+hipError_t launch_ctu_f32_roe(const FusedArgs<float>& a, int recon, int waves, bool fast, int grid, hipStream_t st);
 
 template <bool PPM, int RS, int WAVES, bool FAST>
 static hipError_t launch_one(const FusedArgs<float>& a, int grid, hipStream_t st) {
@@ -16,12 +20,11 @@ static hipError_t launch_one(const FusedArgs<float>& a, int grid, hipStream_t st
 
 template <int WAVES, bool FAST>
 static hipError_t launch_wf(const FusedArgs<float>& a, int recon, int riemann, int grid, hipStream_t st) {
+  if (riemann == 0) return launch_ctu_f32_roe(a, recon, WAVES, FAST, grid, st);
   if (recon == 1) {
-    if (riemann == 0) return launch_one<true, 0, WAVES, FAST>(a, grid, st);
     if (riemann == 1) return launch_one<true, 1, WAVES, FAST>(a, grid, st);
     return launch_one<true, 2, WAVES, FAST>(a, grid, st);
   }
-  if (riemann == 0) return launch_one<false, 0, WAVES, FAST>(a, grid, st);
   if (riemann == 1) return launch_one<false, 1, WAVES, FAST>(a, grid, st);
   return launch_one<false, 2, WAVES, FAST>(a, grid, st);
 }
