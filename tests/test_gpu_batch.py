@@ -381,3 +381,59 @@ def test_vl_box_segments_in_one_launch(H):
     torch.cuda.synchronize()
     assert torch.isnan(o0).all()
     assert torch.equal(o1, alone[1])
+
+
+def test_amr_graph_replay_matches_eager(H):
+    """The AMR preparation (group map, padded fill), the flux accumulation and
+    the coarse-grid correction captured in a HIP graph: three replays, with
+    eager resets of the in-place buffers between them, each equal to the
+    eager result bit for bit (no memset node, no allocation inside)."""
+    rng = np.random.default_rng(71)
+    n, g = 32, 3
+    lay = torch.from_numpy(np.array([[0, 16, 16, 16], [0, 32, 16, 16], [0, 48, 16, 16], [0, 0, 48, 0]],
+                                    dtype=np.int32)).cuda()
+    f32 = torch.float32
+    fine = _dev(rng.random((4, 5, 16, 16, 16)) + 1.0, f32)
+    c0 = _dev(rng.random((5, 8, 8, 8)) + 1.0, f32)
+    c1 = _dev(rng.random((5, 8, 8, 8)) + 1.0, f32)
+    coarse0 = _dev(rng.random((8, 5, 16, 16, 16)) + 1.0, f32)
+    cflux = _dev(rng.standard_normal((8, 3, 3, 5, 16, 16)), f32)
+    fl = _dev(rng.standard_normal((4, 3, 2, 5, 16, 16)), f32)
+    amap = torch.empty(H.group_map_len(4, 1), dtype=torch.int32, device="cuda")
+    fmap = torch.empty(H.group_map_len(n // 8, 1), dtype=torch.int32, device="cuda")
+    pad = torch.empty((4, 5, 22, 22, 22), dtype=f32, device="cuda")
+    acc = torch.zeros_like(fl)
+    coarse = coarse0.clone()
+
+    def cycle():
+        H.build_group_map(lay, 4, 1, out=amap)
+        H.build_group_map(lay, n // 8, 1, out=fmap)
+        H.fill_groups_amr(fine, lay, amap, 4, [0.25], c0, c1, g, out=pad)
+        H.accumulate(acc, fl, 0.5)
+        H.amr_correct(coarse, n, cflux, fine, lay, fmap, acc, 1e-3, 1.0 / n)
+
+    def reset():
+        acc.zero_()
+        coarse.copy_(coarse0)
+        pad.zero_()
+        amap.zero_()
+        fmap.zero_()
+
+    reset()
+    cycle()
+    torch.cuda.synchronize()
+    want = [t.clone() for t in (amap, fmap, pad, acc, coarse)]
+    reset()
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        cycle()
+    for r in range(3):
+        reset()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for got, w in zip((amap, fmap, pad, acc, coarse), want):
+            assert torch.equal(got, w), r
+    assert not torch.equal(coarse, coarse0)
