@@ -27,6 +27,11 @@ PLM, PPM = 0, 1
 ROE, HLLC, HLLE, EXACT = 0, 1, 2, 3
 GMINMOD, VANLEER, VANALBADA, HYBRID = 0, 1, 2, 3
 F_CHAR, F_FLUX_MID, F_ROE_FB_HLLC, F_ROE_FB_EXACT = 0x02, 0x04, 0x10, 0x80
+# Oracle-only switches (the HIP library has neither): the unlimited centred
+# slope, and no PPM edge clipping or monotonization.  They let the pins check
+# the convergence of the linear scheme underneath the limiters.
+CENTRAL = 4
+F_NO_MONO = 0x100
 
 
 def build(force: bool = True) -> None:
@@ -81,6 +86,10 @@ def _lib(counting: bool = False) -> ctypes.CDLL:
     L.oracle_ppm_edge.restype = None
     L.oracle_char.argtypes = [P, P, d, P, P]
     L.oracle_char.restype = None
+    L.oracle_ctu_trace.argtypes = [P, P, P, i, d, d, P, P]
+    L.oracle_ctu_trace.restype = None
+    L.oracle_ppm_monotonize.argtypes = [P, P, P]
+    L.oracle_ppm_monotonize.restype = None
     L.oracle_ghost_width.argtypes = [i, i]
     L.oracle_ghost_width.restype = i
     L.oracle_get_stats.argtypes = [P]
@@ -258,6 +267,22 @@ def ppm_edge(wa, wb, sa, sb) -> np.ndarray:
     e = np.empty(5)
     _lib().oracle_ppm_edge(_p(_f64(wa)), _p(_f64(wb)), _p(_f64(sa)), _p(_f64(sb)), _p(e))
     return e
+
+
+def ctu_trace(w, wl, wr, ppm, dtdh, gamma):
+    """CTU characteristic tracing of one cell in its direction's frame
+    (normal velocity first): returns the half-step states (left face, right
+    face) from the cell state w and its reconstructed face values wl, wr."""
+    ol, orr = np.empty(5), np.empty(5)
+    _lib().oracle_ctu_trace(_p(_f64(w)), _p(_f64(wl)), _p(_f64(wr)), int(ppm), dtdh, gamma, _p(ol), _p(orr))
+    return ol, orr
+
+
+def ppm_monotonize(w, wl, wr):
+    """PPM parabola monotonization of one cell: returns the new (wl, wr)."""
+    a, b = _f64(wl).copy(), _f64(wr).copy()
+    _lib().oracle_ppm_monotonize(_p(_f64(w)), _p(a), _p(b))
+    return a, b
 
 
 def char_roundtrip(w, dw, gamma):

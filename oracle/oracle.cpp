@@ -93,6 +93,13 @@ enum { R_PLM = 0, R_PPM = 1 };
 enum { RS_ROE = 0, RS_HLLC = 1, RS_HLLE = 2, RS_EXACT = 3 };
 enum { L_GMINMOD = 0, L_VANLEER = 1, L_VANALBADA = 2, L_HYBRID = 3 };
 enum { F_CHAR = 0x02, F_FLUX_MID = 0x04, F_ROE_FB_HLLC = 0x10, F_ROE_FB_EXACT = 0x80 };
+// Oracle-only switches that turn the nonlinear parts of the reconstruction
+// off, so that the smooth-data convergence of the underlying linear scheme
+// can be pinned on its own: L_CENTRAL takes the unlimited centred slope,
+// F_NO_MONO skips the PPM edge clipping and the parabola monotonization.
+// The HIP library has neither.
+enum { L_CENTRAL = 4 };
+enum { F_NO_MONO = 0x100 };
 
 struct V5 {
   real v[5];
@@ -107,7 +114,7 @@ struct Cfg {
   real theta;        // generalized-minmod parameter
   real floor;        // density and pressure floor for face / half-step states
   int scheme, recon, riemann, limiter;
-  bool charlim, fb_hllc, fb_exact;
+  bool charlim, fb_hllc, fb_exact, no_mono;
 };
 
 struct Stats {
@@ -190,6 +197,7 @@ static void apply_floor(V5& W, const Cfg& c) {
 // extremum (dl*dr <= 0).
 // ---------------------------------------------------------------------------
 static real limit_slope(real dl, real dr, const Cfg& c) {
+  if (c.limiter == L_CENTRAL) return 0.5 * (dl + dr);
   if (dl * dr <= 0.0) return 0.0;
   real dc = 0.5 * (dl + dr);
   switch (c.limiter) {
@@ -249,13 +257,13 @@ static V5 limited_slope(const V5& wm, const V5& w0, const V5& wp, const Cfg& c) 
 }
 
 // PPM edge value between cells a and b from their states and limited slopes,
-// clipped into the range of the two cell values.
-static V5 ppm_edge(const V5& wa, const V5& wb, const V5& sa, const V5& sb) {
+// clipped into the range of the two cell values (unless `clip` is false).
+static V5 ppm_edge(const V5& wa, const V5& wb, const V5& sa, const V5& sb, bool clip = true) {
   V5 e;
   for (int n = 0; n < 5; ++n) {
     real v = 0.5 * (wa[n] + wb[n]) - (sb[n] - sa[n]) / 6.0;
     real lo = r_min(wa[n], wb[n]), hi = r_max(wa[n], wb[n]);
-    e[n] = r_min(r_max(v, lo), hi);
+    e[n] = clip ? r_min(r_max(v, lo), hi) : v;
   }
   return e;
 }
@@ -277,6 +285,14 @@ static void ppm_monotonize(const V5& w, V5& wl, V5& wr) {
     wl[n] = l;
     wr[n] = r;
   }
+}
+
+// Curvature coefficient of the parabola through the face values wl, wr with
+// cell mean w: W6 = 6 (W - (WL + WR) / 2).
+static V5 ppm_w6(const V5& w, const V5& wl, const V5& wr) {
+  V5 w6;
+  for (int n = 0; n < 5; ++n) w6[n] = 6.0 * (w[n] - 0.5 * (wl[n] + wr[n]));
+  return w6;
 }
 
 // Characteristic tracing to t+dt/2 (CTU step (1)): Colella's reference-state
@@ -626,10 +642,10 @@ static Range face_states(const Grid& g, const Field& W, Range wr, int d, const C
     V5 wl, wr2, w6;
     if (ppm) {
       V5 wm = to_frame(W[im], d), wp = to_frame(W[ip], d);
-      wl = ppm_edge(wm, w, S[im], S[ic]);
-      wr2 = ppm_edge(w, wp, S[ic], S[ip]);
-      ppm_monotonize(w, wl, wr2);
-      for (int n = 0; n < 5; ++n) w6[n] = 6.0 * (w[n] - 0.5 * (wl[n] + wr2[n]));
+      wl = ppm_edge(wm, w, S[im], S[ic], !c.no_mono);
+      wr2 = ppm_edge(w, wp, S[ic], S[ip], !c.no_mono);
+      if (!c.no_mono) ppm_monotonize(w, wl, wr2);
+      w6 = ppm_w6(w, wl, wr2);
     } else {
       for (int n = 0; n < 5; ++n) {
         wl[n] = w[n] - 0.5 * S[ic][n];
@@ -803,7 +819,7 @@ static int make_cfg(Cfg& c, double dt, double dh, double gamma, int scheme, int 
                     int flags) {
   if (!(dt > 0.0) || !(dh > 0.0) || !(gamma > 1.0)) return -1;
   if (scheme < 0 || scheme > 2 || recon < 0 || recon > 1 || riemann < 0 || riemann > 3 || limiter < 0 ||
-      limiter > 3)
+      limiter > L_CENTRAL)
     return -1;
   c.gamma = gamma;
   c.gm1 = gamma - 1.0;
@@ -818,6 +834,7 @@ static int make_cfg(Cfg& c, double dt, double dh, double gamma, int scheme, int 
   c.charlim = (flags & F_CHAR) != 0;
   c.fb_hllc = (flags & F_ROE_FB_HLLC) != 0;
   c.fb_exact = (flags & F_ROE_FB_EXACT) != 0;
+  c.no_mono = (flags & F_NO_MONO) != 0;
   return 0;
 }
 
@@ -1250,6 +1267,30 @@ void oracle_char(const double* w, const double* dw, double gamma, double* a, dou
   V5 A = char_project(W, cs, D);
   V5 B = char_expand(W, cs, A);
   for (int n = 0; n < 5; ++n) { a[n] = to_d(A[n]); back[n] = to_d(B[n]); }
+}
+
+// Characteristic tracing of one cell (CTU step (1)) in the frame of its
+// direction (normal velocity first): cell state w, face values wl (left face)
+// and wr (right face) from the reconstruction, Courant factor dtdh = dt/dh.
+// ppm = 1 uses the parabola through wl, wr with mean w (W6 from ppm_w6);
+// ppm = 0 the linear profile from wl to wr.  Writes the half-step states at
+// the left face (out_l) and the right face (out_r); no floors are applied.
+void oracle_ctu_trace(const double* w, const double* wl, const double* wr, int ppm, double dtdh, double gamma,
+                      double* out_l, double* out_r) {
+  Cfg c;
+  make_cfg(c, dtdh, 1.0, gamma, S_CTU, ppm ? R_PPM : R_PLM, 0, 0, 0);
+  V5 W, L, R, w6;
+  for (int n = 0; n < 5; ++n) { W[n] = w[n]; L[n] = wl[n]; R[n] = wr[n]; w6[n] = 0.0; }
+  if (ppm) w6 = ppm_w6(W, L, R);
+  ctu_trace(W, L, R, w6, ppm != 0, c);
+  for (int n = 0; n < 5; ++n) { out_l[n] = to_d(L[n]); out_r[n] = to_d(R[n]); }
+}
+// PPM parabola monotonization of one cell (per component, in place).
+void oracle_ppm_monotonize(const double* w, double* wl, double* wr) {
+  V5 W, L, R;
+  for (int n = 0; n < 5; ++n) { W[n] = w[n]; L[n] = wl[n]; R[n] = wr[n]; }
+  ppm_monotonize(W, L, R);
+  for (int n = 0; n < 5; ++n) { wl[n] = to_d(L[n]); wr[n] = to_d(R[n]); }
 }
 
 void oracle_reset_stats(void) { std::memset(&g_stats, 0, sizeof(g_stats)); }

@@ -436,6 +436,11 @@ def _wave_error(oracle, scheme, recon, n, kvec, dims, cfl=0.4, gamma=5.0 / 3.0):
     return np.abs(U[0] - U0[0]).mean()
 
 
+# With the limiters on, MHM+PPM and VL+PPM lose order (about 1.5 here): the
+# van Leer slopes, the edge clipping and the monotonization flatten the
+# parabolas at the wave's smooth extrema.  The same schemes with the limiting
+# switched off converge at second order (test_oracle_pins_tracing.py), so the
+# lower bound here is a regression check of the limited scheme, not its order.
 @pytest.mark.parametrize("scheme,recon,min_order", [(0, 0, 1.9), (1, 0, 1.9), (2, 0, 1.9), (2, 1, 1.9),
                                                     (0, 1, 1.5), (1, 1, 1.4)])
 def test_convergence_1d(oracle, scheme, recon, min_order):
