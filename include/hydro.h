@@ -292,6 +292,24 @@ int hydro_step_box(const void* box_in, void* box_out, void* flux_out, int nx, in
 int hydro_cfl_dt_batch(const struct hydro_seg* segs, int n_segs, long long n_groups_total, double gamma, double cfl,
                        int flags, void* stream);
 
+/*
+ * hydro_cfl_dt_batch for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, layouts, results (bit for bit) and errors as
+ * hydro_cfl_dt_batch, but it calls no hipMalloc / hipFree: the per-group
+ * maxima go to a library-owned static device array of
+ * HYDRO_NOALLOC_MAX_GROUPS doubles (8 MiB, one copy on every device the
+ * library runs on, held until the process ends).  Every slot a call reads
+ * is written by the same call first, so nothing needs clearing.
+ * n_groups_total > HYDRO_NOALLOC_MAX_GROUPS -> HYDRO_EINVAL (checked before
+ * any device call).  All calls on one device share that array: calls
+ * ordered on one stream are safe, calls that overlap in time on one device
+ * (unordered streams) race and give wrong time steps.
+ */
+#define HYDRO_NOALLOC_MAX_GROUPS (1 << 20)
+int hydro_cfl_dt_batch_noalloc(const struct hydro_seg* segs, int n_segs, long long n_groups_total, double gamma,
+                               double cfl, int flags, void* stream);
+
 /* Specialization of a batched launch (all segments share it). */
 struct hydro_spec {
   int scheme, reconstruction, riemann, limiter, flags;

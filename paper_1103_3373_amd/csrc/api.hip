@@ -246,6 +246,35 @@ int run_fused(const hy::Seg* segs_dev, int n_segs, long long n_groups, int g, in
 
 }  // namespace
 
+// Per-group maxima of hydro_cfl_dt_batch_noalloc: a static device array, one
+// copy per device.  In host code its name is only a host-side stand-in, so
+// host code never passes it to a kernel or a copy; it uses the address that
+// hipGetSymbolAddress returns on each device, resolved once per device.
+static __device__ __align__(256) double scratch[HYDRO_NOALLOC_MAX_GROUPS];
+
+namespace {
+
+std::map<int, double*> g_scratch;  // device -> address of `scratch` there (guarded by g_mu)
+
+// Address of `scratch` on the current device; resolves it on the first call
+// there (no allocation: the array is part of the library's code object).
+int scratch_on_device(double** out) {
+  int dev;
+  if (int rc = current_device(&dev)) return rc;
+  auto it = g_scratch.find(dev);
+  if (it == g_scratch.end()) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return fail(HYDRO_EHIP, "hipGetSymbolAddress(scratch) returned a null address");
+    it = g_scratch.emplace(dev, static_cast<double*>(ptr)).first;
+  }
+  *out = it->second;
+  return 0;
+}
+
+}  // namespace
+
 extern "C" {
 
 int hydro_ghost_width(int scheme, int reconstruction) { return ghost_width(scheme, reconstruction); }
@@ -466,6 +495,27 @@ int hydro_cfl_dt_batch(const struct hydro_seg* segs, int n_segs, long long n_gro
   hipError_t e = hy::launch_seg_dt((const hy::Seg*)segs, n_segs, n_groups_total, gamma, cfl, (flags & HYDRO_F64) ? 1 : 0,
                                    w.seg_partial, st);
   if (e != hipSuccess) return hip_fail(e, "batched dt");
+  return 0;
+}
+
+int hydro_cfl_dt_batch_noalloc(const struct hydro_seg* segs, int n_segs, long long n_groups_total, double gamma,
+                               double cfl, int flags, void* stream) {
+  g_err[0] = 0;
+  if (n_segs < 0 || n_groups_total < 0) return fail(HYDRO_EINVAL, "negative sizes");
+  if (n_groups_total > HYDRO_NOALLOC_MAX_GROUPS)
+    return fail(HYDRO_EINVAL, "n_groups_total %lld exceeds the static scratch of %d groups", n_groups_total,
+                HYDRO_NOALLOC_MAX_GROUPS);
+  if (n_groups_total == 0) return 0;
+  if (!segs || n_segs == 0) return fail(HYDRO_EINVAL, "null segment table");
+  if (!(gamma > 1.0) || !(cfl > 0.0)) return fail(HYDRO_EINVAL, "cfl > 0 and gamma > 1 required");
+  if (flags & ~kKnownFlags) return fail(HYDRO_EINVAL, "unknown flag bits");
+  hipStream_t st = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lock(g_mu);
+  double* partial;
+  if (int rc = scratch_on_device(&partial)) return rc;
+  hipError_t e = hy::launch_seg_dt((const hy::Seg*)segs, n_segs, n_groups_total, gamma, cfl, (flags & HYDRO_F64) ? 1 : 0,
+                                   partial, st);
+  if (e != hipSuccess) return hip_fail(e, "batched dt (static scratch)");
   return 0;
 }
 

@@ -21,12 +21,13 @@ ROE, HLLC, HLLE, EXACT = 0, 1, 2, 3
 GMINMOD, VANLEER, VANALBADA, HYBRID = 0, 1, 2, 3
 F64, CHAR, FLUX_MID, PLAIN, ROE_FB_HLLC, BOX_GROUPED, BOX_SEGS, ROE_FB_EXACT = 0x01, 0x02, 0x04, 0x08, 0x10, 0x20, \
     0x40, 0x80
+NOALLOC_MAX_GROUPS = 1 << 20  # HYDRO_NOALLOC_MAX_GROUPS
 
 EXPORTS = (
     "hydro_ghost_width", "hydro_solve_groups", "hydro_cfl_dt", "hydro_conserved_sums", "hydro_cfl_dt_sums",
     "hydro_fill_ghosts_periodic", "hydro_fill_groups_interp", "hydro_group_map_len", "hydro_build_group_map",
     "hydro_fill_groups_amr", "hydro_amr_correct", "hydro_accumulate", "hydro_solve_batch", "hydro_autotune",
-    "hydro_set_launch_shape", "hydro_step_box", "hydro_cfl_dt_batch",
+    "hydro_set_launch_shape", "hydro_step_box", "hydro_cfl_dt_batch", "hydro_cfl_dt_batch_noalloc",
     "hydro_get_diag", "hydro_last_error", "hydro_shutdown",
 )
 
@@ -93,6 +94,8 @@ def lib() -> ctypes.CDLL:
     L.hydro_step_box.restype = i
     L.hydro_cfl_dt_batch.argtypes = [P, i, ll, d, d, i, P]
     L.hydro_cfl_dt_batch.restype = i
+    L.hydro_cfl_dt_batch_noalloc.argtypes = [P, i, ll, d, d, i, P]
+    L.hydro_cfl_dt_batch_noalloc.restype = i
     L.hydro_solve_batch.argtypes = [P, i, ll, ctypes.POINTER(Spec), P]
     L.hydro_solve_batch.restype = i
     L.hydro_autotune.argtypes = [ctypes.POINTER(Spec), i, P]
@@ -359,6 +362,15 @@ def cfl_dt_batch(seg_dev: torch.Tensor, n_segs: int, n_groups_total: int, *, gam
     """FP64 dt of every segment's `out` state, written to its dt pointer."""
     _check("hydro_cfl_dt_batch", lib().hydro_cfl_dt_batch(_ptr(seg_dev), n_segs, int(n_groups_total), float(gamma),
                                                           float(cfl), F64 if f64 else 0, _stream(stream)))
+
+
+def cfl_dt_batch_noalloc(seg_dev: torch.Tensor, n_segs: int, n_groups_total: int, *, gamma, cfl, f64=False,
+                         stream=None):
+    """cfl_dt_batch without device allocation (library-owned static scratch of
+    NOALLOC_MAX_GROUPS groups; calls that overlap in time on one device race)."""
+    _check("hydro_cfl_dt_batch_noalloc",
+           lib().hydro_cfl_dt_batch_noalloc(_ptr(seg_dev), n_segs, int(n_groups_total), float(gamma), float(cfl),
+                                            F64 if f64 else 0, _stream(stream)))
 
 
 def autotune(spec: Spec, n_groups_hint: int, stream=None) -> int:

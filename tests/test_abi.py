@@ -175,3 +175,20 @@ def test_amr_correct_validation(L):
     assert acc(P(0x1000), P(0x1000 + 4), 0.5, 4, 0, None) == EALIAS
     assert acc(P(0), P(0x2000), 0.5, 4, 0, None) == EINVAL
     assert acc(P(0x1000), P(0x2000), 0.5, 0, 0, None) == 0
+
+
+def test_noalloc_dt_rejects_sizes_before_device_calls(L):
+    """The allocation-free batched dt rejects batches beyond its static
+    scratch (and bad arguments) before any device call; an empty batch is a
+    no-op.  The fake table address is never dereferenced."""
+    from paper_1103_3373_amd import hydro
+    P = ctypes.c_void_p
+    call = lambda n_segs, n, gamma=1.4, cfl=0.5, flags=0: L.hydro_cfl_dt_batch_noalloc(
+        P(0x1000), n_segs, ctypes.c_longlong(n), gamma, cfl, flags, None)
+    assert call(1, hydro.NOALLOC_MAX_GROUPS + 1) == -1
+    assert b"static scratch" in L.hydro_last_error()
+    assert call(1, 1 << 40) == -1
+    assert call(-1, 8) == -1
+    assert call(1, -8) == -1
+    assert call(0, 0) == 0
+    assert call(1, 0) == 0
