@@ -44,8 +44,11 @@ METRIC = "cell-updates/s at 256^3 CTU+PPM+HLLC vs plain; HBM roofline %; p50/p99
 OPS_PER_CELL = 2693.9
 # The same count for the other schemes of the 256^3 workload (PPM(char) + HLLC).
 OPS_PER_CELL_SCHEME = {"MHM": 1607.9, "VL": 1775.9, "CTU": OPS_PER_CELL}
-# Non-packed FP32 VALU peak: 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz.
-ALU_PEAK = 256 * 64 * 2 * 2.4e9
+# Published FP32 vector peak of MI355X: 256 CU x 4 SIMD x 16 lanes x 2 flop
+# (FMA) x 2 (packed FP32) x 2.4 GHz = 157.3 TFLOP/s.  The kernels are built
+# without packed FP32 instructions, so their own ceiling is half of it.
+ALU_PEAK = 256 * 4 * 16 * 2 * 2 * 2.4e9
+ALU_PEAK_NONPACKED = ALU_PEAK / 2
 HBM_PEAK = 8.0e12
 # Algorithmic HBM bytes per cell update of the box solver (FP32): read U^n and
 # write U^{n+1} once each (5 x 4 B each way); ghost cells come from
@@ -60,7 +63,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--n", type=int, default=256, help="box size (multiple of 16)")
     p.add_argument("--plain-steps", type=int, default=2)
-    p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--cpu-seconds", type=float, default=8.0)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--extra-reps", type=int, default=10,
@@ -106,16 +109,39 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def cpu_baseline(ghosted_dev, dt: float, dh: float, gamma: float, budget_s: float):
-    """The FP64 oracle, single-threaded, on the leading groups of the same
-    ghosted input (copied to the host 32 groups at a time) until the time
-    budget is used."""
+def host_cpu():
+    """CPU model, logical CPUs and the CPUs this process may use."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return model, os.cpu_count(), usable
+
+
+def cpu_baseline(ghosted_dev, dt: float, dh: float, gamma: float, budget_s: float, box64_seed: int):
+    """The FP64 oracle on the host cores, on the same first-step input as the
+    GPU (CTU + PPM(char) + HLLC, ghosted groups copied to the host):
+      * one thread on the leading groups until the time budget is used;
+      * all usable cores (up to 16 worker processes, one share of the groups
+        each: the analog of threading over patches) on every group;
+      * one thread on whole 64^3 periodic boxes, 10 steps of MHM, VL and CTU
+        (PPM(char) + HLLC, CFL 0.3 / 0.3 / 0.5), and the 32^3 Sod case of the
+        plain path (MHM + PLM(primitive, van Leer) + Roe, gamma 5/3) in full,
+        10 steps at CFL 0.5."""
     import oracle as O
+    from paper_1103_3373_amd import workloads as W
     O._lib()
+    model, ncpu, usable = host_cpu()
+    workers = max(1, min(16, usable))
     total = ghosted_dev.shape[0]
+    # One thread, bounded sample.
     t0 = time.perf_counter()
-    done = 0
-    el = 0.0
+    done, el = 0, 0.0
     while done < total and el < budget_s:
         chunk = ghosted_dev[done:done + 32].cpu().numpy().astype(np.float64)
         for q in range(chunk.shape[0]):
@@ -125,9 +151,40 @@ def cpu_baseline(ghosted_dev, dt: float, dh: float, gamma: float, budget_s: floa
             done += 1
             if el >= budget_s:
                 break
-    return {"value": done * 4096 / el, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} of {total} patch groups of the same first-step input (CTU+PPM(char)+HLLC), "
-                      f"FP64 oracle (g++ -O2), one thread, {el:.1f} s of oracle time"}
+    one = done * 4096 / el
+    # All usable cores, every group of the step.
+    host = ghosted_dev.cpu().numpy()
+    with O.GroupPool(workers) as pool:
+        pool.solve_groups(host[:workers].astype(np.float64), 3, dt, dh, gamma, O.CTU, O.PPM, O.HLLC, O.VANLEER,
+                          O.F_CHAR)  # workers started and warm
+        t1 = time.perf_counter()
+        pool.solve_groups(host.astype(np.float64), 3, dt, dh, gamma, O.CTU, O.PPM, O.HLLC, O.VANLEER, O.F_CHAR)
+        el_all = time.perf_counter() - t1
+    del host
+    allc = total * 4096 / el_all
+    # Whole 64^3 boxes, 10 steps per scheme, one thread.
+    box64 = W.lognormal_blast_box(64, gamma=gamma, seed=box64_seed, radius_cells=2)
+    per_scheme = {}
+    for scheme, name, cfl in ((O.MHM, "MHM", 0.3), (O.VL, "VL", 0.3), (O.CTU, "CTU", 0.5)):
+        st = box64.copy()
+        t1 = time.perf_counter()
+        for _ in range(10):
+            st = O.step_box(st, O.cfl_dt(st, 1 / 64, gamma, cfl), 1 / 64, gamma, scheme, O.PPM, O.HLLC, O.VANLEER,
+                            O.F_CHAR)
+        per_scheme[name] = 10 * 64 ** 3 / (time.perf_counter() - t1)
+    sod = W.sod_box(32, gamma=5.0 / 3.0)
+    t1 = time.perf_counter()
+    for _ in range(10):
+        sod = O.step_box(sod, O.cfl_dt(sod, 1 / 32, 5.0 / 3.0, 0.5), 1 / 32, 5.0 / 3.0, O.MHM, O.PLM, O.ROE,
+                         O.VANLEER, 0)
+    c1 = 10 * 32 ** 3 / (time.perf_counter() - t1)
+    return {"value": allc, "unit": "cell-updates/s", "cores": workers, "kind": "oracle",
+            "sample": f"all {total} patch groups of the same first-step input (CTU+PPM(char)+HLLC, FP64 oracle, "
+                      f"g++ -O2) split over {workers} worker processes ({el_all:.1f} s); one thread: {done} groups "
+                      f"in {el:.1f} s; whole 64^3 boxes x 10 steps per scheme and the 32^3 Sod case x 10 steps, "
+                      f"one thread",
+            "per_core_value": one, "cpu_model": model, "nproc": ncpu, "usable_cpus": usable,
+            "box64_10_steps_one_thread": per_scheme, "sod32_mhm_plm_roe_fp64_one_thread": c1}
 
 
 def amr_bench(args):
@@ -523,7 +580,7 @@ def main():
         ghosted = H.fill_ghosts_periodic(first, g, grouped=True, shape=(n, n, n))
         del first
         torch.cuda.synchronize()
-        cpu = cpu_baseline(ghosted, dt0, dh, gamma, args.cpu_seconds)
+        cpu = cpu_baseline(ghosted, dt0, dh, gamma, args.cpu_seconds, W.IC_SEED)
         del ghosted
 
     src_hash = kernel_source_hash()
@@ -552,6 +609,7 @@ def main():
         "solver_cell_updates_per_s": cells / (kern_avg * 1e-3),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / ALU_PEAK, "traffic": traffic,
+                     "peak_nonpacked": ALU_PEAK_NONPACKED / 1e12, "frac_of_nonpacked": achieved / ALU_PEAK_NONPACKED,
                      "ops_per_cell": OPS_PER_CELL, "kernel": "ctu_fused_kernel<float, PPM, HLLC>",
                      "kernel_source_sha256": src_hash},
         "hbm": {"algorithmic_bytes_per_cell": BYTES_PER_CELL,

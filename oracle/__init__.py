@@ -147,6 +147,42 @@ def solve_groups(G, g, dt, dh, gamma, scheme, recon, riemann, limiter, flags=0, 
     return out, flux
 
 
+def _solve_chunk(args):
+    return solve_groups(*args)[0]
+
+
+class GroupPool:
+    """Worker processes that each run solve_groups on a share of a batch of
+    patch groups: the host-side analog of threading one step over patches
+    (Sec. 4.3).  The arithmetic of every group is solve_groups's own; only
+    the groups are split between processes (spawned, so a parent that has
+    initialised a GPU is never forked)."""
+
+    def __init__(self, workers: int):
+        import multiprocessing as mp
+        self.workers = int(workers)
+        self._pool = mp.get_context("spawn").Pool(self.workers, initializer=_lib)
+
+    def solve_groups(self, G, g, dt, dh, gamma, scheme, recon, riemann, limiter, flags=0) -> np.ndarray:
+        """out[n][5][16][16][16] of solve_groups(G, ...), groups split in
+        contiguous chunks (a few per worker)."""
+        G = _f64(G)
+        chunks = [c for c in np.array_split(np.arange(G.shape[0]), 4 * self.workers) if len(c)]
+        outs = self._pool.map(_solve_chunk, [(G[c[0]:c[-1] + 1], g, dt, dh, gamma, scheme, recon, riemann,
+                                              limiter, flags) for c in chunks])
+        return np.concatenate(outs) if outs else np.empty((0, 5, 16, 16, 16))
+
+    def close(self):
+        self._pool.close()
+        self._pool.join()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
 def fill_ghosts_periodic(box, g) -> np.ndarray:
     """box[5][nz][ny][nx] -> padded groups [G][5][16+2g]^3 (periodic wrap)."""
     box = _f64(box)

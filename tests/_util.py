@@ -26,12 +26,12 @@ def random_smooth_box(n, gamma, seed, amp=0.2, ny=None, nz=None):
     return W.primitive_to_conserved(rho, amp * fields[1], amp * fields[2], amp * fields[3], p, gamma)
 
 
-def rel_errors(a, b):
+def rel_errors(a, b, axis=None):
     """Per-variable (rel_L1, rel_Linf) of a against reference b; arrays [..., 5, ...]
-    with the variable on axis 1 (groups) or 0 (box)."""
+    with the variable on axis 1 (groups) or 0 (box), or on `axis`."""
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
-    ax = 1 if a.ndim in (5, 6) else 0
+    ax = axis if axis is not None else (1 if a.ndim in (5, 6) else 0)
     a = np.moveaxis(a, ax, 0).reshape(5, -1) if a.shape[ax] == 5 else a.reshape(1, -1)
     b = np.moveaxis(b, ax, 0).reshape(5, -1) if b.shape[ax] == 5 else b.reshape(1, -1)
     d = np.abs(a - b)
@@ -63,3 +63,16 @@ def field_errors(a, b):
     s1 = np.array([np.abs(b[0]).sum()] + [mag.sum()] * 3 + [np.abs(b[4]).sum()])
     si = np.array([np.abs(b[0]).max()] + [mag.max()] * 3 + [np.abs(b[4]).max()])
     return d.sum(1) / np.maximum(s1, 1e-300), d.max(1) / np.maximum(si, 1e-300)
+
+
+def group_window(box, q, g):
+    """The ghosted input of patch group q (width g) of a periodic box
+    [5][nz][ny][nx], cut out with periodic index wrap: [5][16+2g]^3.  Group
+    order (gz*ngy + gy)*ngx + gx.  Indexing only (no solver arithmetic)."""
+    nz, ny, nx = box.shape[1:]
+    ngx, ngy = nx // 16, ny // 16
+    gx, gy, gz = q % ngx, (q // ngx) % ngy, q // (ngx * ngy)
+    ix = np.arange(16 * gx - g, 16 * gx + 16 + g) % nx
+    iy = np.arange(16 * gy - g, 16 * gy + 16 + g) % ny
+    iz = np.arange(16 * gz - g, 16 * gz + 16 + g) % nz
+    return box[:, iz][:, :, iy][:, :, :, ix]

@@ -1,0 +1,100 @@
+"""Full-size parity of the benchmarked path: one step of the 256^3 periodic
+box (4096 patch groups) in box mode, FP32 CTU + PPM (characteristic, van
+Leer) + HLLC, gamma 1.4, on the seeded lognormal + blast input, with the
+launch shape the autotuner picks for it (as the benchmark does) and with
+pinned shapes.
+
+Sampled groups are compared element by element with the FP64 oracle on the
+same FP32-rounded input, relative L1 and Linf <= 1e-5 per conserved
+variable: groups at the periodic wrap (box corners and faces), at the
+boundaries of the per-XCD chunks of the persistent launch order (eighths of
+the group range), and the groups holding the largest pressure (blast
+regions).  Results must not depend on the launch shape (bit-identical), and
+the whole box conserves mass and energy to FP32 round-off."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1103_3373_amd import workloads as W
+from tests._util import group_window, rel_errors
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+N = 256
+GAMMA = 1.4
+
+
+@pytest.fixture(scope="module")
+def case():
+    from paper_1103_3373_amd import hydro as H
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    box = W.lognormal_blast_box(N, gamma=GAMMA, seed=W.IC_SEED).astype(np.float32).astype(np.float64)
+    state = torch.from_numpy(W.box_to_groups(box).astype(np.float32)).cuda()
+    dt_dev = torch.empty(1, dtype=torch.float64, device="cuda")
+    H.cfl_dt(state, 1.0 / N, GAMMA, 0.5, dt_out=dt_dev)
+    torch.cuda.synchronize()
+    return H, box, state, dt_dev
+
+
+def _step(H, state, dt_dev):
+    out = torch.empty_like(state)
+    H.step_box(state, out, (N, N, N), dt_dev, dh=1.0 / N, gamma=GAMMA, scheme=H.CTU, recon=H.PPM, riemann=H.HLLC,
+               limiter=H.VANLEER, char=True)
+    torch.cuda.synchronize()
+    return out
+
+
+def _sample(box):
+    ng = N // 16
+    G = ng ** 3
+    corners = [0, ng - 1, ng * (ng - 1), ng * ng * (ng - 1), G - 1]
+    faces = [ng * ng * 7 + ng * 7, ng * ng * 7 + 7, 7 * ng + 7, ng * ng * 7 + ng * 7 + ng - 1]
+    chunk = (G + 7) // 8
+    xcd = sorted({c for k in range(1, 8) for c in (k * chunk - 1, k * chunk)})
+    # groups holding the largest total energy (the blasts): flat index
+    # (gz*ng + gy)*ng + gx is the group order
+    e_max = box[4].reshape(ng, 16, ng, 16, ng, 16).max(axis=(1, 3, 5)).reshape(-1)
+    p_max = list(np.argsort(e_max)[-2:])
+    return sorted(set(corners + faces + xcd + [int(q) for q in p_max]))
+
+
+def test_box_256_autotuned_shape_matches_oracle(case):
+    H, box, state, dt_dev = case
+    spec = H.make_spec(H.CTU, H.PPM, H.HLLC, H.VANLEER, gamma=GAMMA, char=True)
+    grid = H.autotune(spec, (N // 16) ** 3)
+    assert grid > 0
+    out = _step(H, state, dt_dev)
+    assert torch.isfinite(out).all().item()
+    dt = dt_dev.item()
+    assert dt == O.cfl_dt(W.box_to_groups(box), 1.0 / N, GAMMA, 0.5)
+    pick = _sample(box)
+    Gs = np.stack([group_window(box, q, 3) for q in pick])
+    ref, _ = O.solve_groups(Gs, 3, dt, 1.0 / N, GAMMA, O.CTU, O.PPM, O.HLLC, O.VANLEER, O.F_CHAR)
+    got = out[pick].cpu().numpy().astype(np.float64)
+    worst = []
+    for k, q in enumerate(pick):
+        l1, linf = rel_errors(got[k], ref[k])
+        worst.append((q, float(l1.max()), float(linf.max())))
+    print("group, worst rel L1, worst rel Linf:", worst)
+    l1, linf = rel_errors(got, ref)
+    assert l1.max() <= 1e-5 and linf.max() <= 1e-5, (l1, linf, worst)
+    for q, a, b in worst:
+        assert a <= 1e-5 and b <= 1e-5, (q, a, b)
+    s0 = H.conserved_sums(state, 1.0 / N).cpu().numpy()
+    s1 = H.conserved_sums(out, 1.0 / N).cpu().numpy()
+    assert abs(s1[0] - s0[0]) <= 1e-6 * abs(s0[0]) and abs(s1[4] - s0[4]) <= 1e-6 * abs(s0[4])
+
+
+@pytest.mark.parametrize("grid,variant", [(4096, 4), (3072, 4), (512, 4), (256, 2), (1000, 2)])
+def test_box_256_result_independent_of_launch_shape(case, grid, variant):
+    H, box, state, dt_dev = case
+    spec = H.make_spec(H.CTU, H.PPM, H.HLLC, H.VANLEER, gamma=GAMMA, char=True)
+    H.set_launch_shape(spec, 0, 4)
+    base = _step(H, state, dt_dev)
+    H.set_launch_shape(spec, grid, variant)
+    try:
+        out = _step(H, state, dt_dev)
+    finally:
+        H.set_launch_shape(spec, 0, 4)
+    assert torch.equal(out, base)

@@ -134,6 +134,29 @@ def test_fp32_one_step_smooth_within_1e5(H, scheme, recon, rs, char):
         assert scaled_max_err(flux, rflux) <= 1e-5
 
 
+@pytest.mark.parametrize("lim", [0, 2, 3])
+@pytest.mark.parametrize("scheme,recon,rs,char", [(0, 0, 0, False), (0, 1, 1, True), (1, 1, 1, True),
+                                                  (1, 0, 2, False), (2, 1, 1, True), (2, 0, 0, False)])
+def test_fp32_limiters_smooth_within_1e5(H, lim, scheme, recon, rs, char):
+    """Generalized minmod, van Albada and hybrid limiters in FP32 (the
+    fused kernels take these through their run-time limiter branch) against
+    the oracle on the FP32-rounded input: relative L1 and Linf <= 1e-5 per
+    conserved variable, fused and plain paths, with face fluxes."""
+    gamma = 1.4
+    box = random_smooth_box(32, gamma, 17 + lim, amp=0.3)
+    g = O.ghost_width(scheme, recon)
+    G = O.fill_ghosts_periodic(box, g).astype(np.float32).astype(np.float64)
+    dt, dh = 4e-3, 1 / 32
+    ref, rflux = O.solve_groups(G, g, dt, dh, gamma, scheme, recon, rs, lim, O.F_CHAR if char else 0,
+                                want_flux=True)
+    for plain in (True, False):
+        out, flux = _run(H, G, g, torch.float32, dt, dh, gamma, scheme, recon, rs, lim, char, plain)
+        l1, linf = rel_errors(out, ref)
+        assert l1.max() <= 1e-5 and linf.max() <= 1e-5, (plain, l1, linf)
+        fl1, flinf = rel_errors(flux, rflux, axis=3)  # [n][dir][face][var][16][16]
+        assert flinf.max() <= 1e-5, (plain, fl1, flinf)
+
+
 @pytest.mark.parametrize("scheme,recon,rs", [(0, 1, 0), (1, 1, 1), (2, 1, 1), (2, 1, 0)])
 def test_fp32_blast_shocks(H, scheme, recon, rs):
     """Lognormal + blasts with shocks: FP32 stays within 1e-5 in relative L1."""

@@ -1,17 +1,21 @@
 """Precision on smooth data: a Kelvin-Helmholtz shear layer (tanh interfaces
-of width 4 cells) advanced 100 steps by the FP32 and FP64 GPU paths and by
-the FP64 oracle on the same time-step sequence, for MHM, VL and CTU
-(PPM with characteristic limiting + HLLC); FP64 conservation sums on the GPU.
+of width 4 cells, gamma 1.4) with PPM (characteristic limiting, van Leer) +
+HLLC.
 
-Errors are L1 norms of the difference per conserved variable, relative to
-the reference's L1 norm of that variable; the momentum components share
-the momentum magnitude |m| as scale (the z momentum of this flow is zero
-everywhere and the y momentum is a small perturbation).
+64^3 (64 patch groups), 100 steps, for MHM, VL and CTU: the FP32 and FP64
+GPU paths and the FP64 oracle advance the same state on the oracle's
+time-step sequence.  Errors are per conserved variable, L1 and Linf of the
+difference relative to the reference's L1 norm / maximum of that variable;
+the three momentum components share the momentum magnitude |m| as scale
+(the z momentum of this flow is zero everywhere and the y momentum is a
+small perturbation).  Bars: FP32 GPU vs oracle <= 1e-5 in L1 and Linf; FP64
+GPU vs oracle <= 1e-12 in L1 and Linf; drift of the FP64 conserved sums of
+mass and energy <= 1e-13 (FP64 path) and <= 1e-6 (FP32 path) relative, of
+the momenta relative to the integral of |m|.
 
-Bars: FP32 GPU vs oracle <= 1e-5; FP64 GPU vs oracle <= 1e-12 after 100
-steps; drift of the FP64 conserved sums of mass and energy <= 1e-13
-(FP64 path) and <= 1e-6 (FP32 path) relative, of the momenta relative to
-the integral of |m|."""
+512^3 (32768 patch groups), 100 CTU steps: the FP32 path against the FP64
+path on the GPU (both with the FP64 path's device time step), the same
+bars as FP32 vs oracle, and the same conservation bars."""
 import numpy as np
 import pytest
 
@@ -23,44 +27,77 @@ from tests._util import field_errors
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-N = 32
 STEPS = 100
+GAMMA = 1.4
+
+
+def _drift_ok(s, s0, mom, rel_mass_energy, rel_mom):
+    for v in (0, 4):
+        assert abs(s[v] - s0[v]) <= rel_mass_energy * abs(s0[v]), (v, s[v], s0[v])
+    for v in (1, 2, 3):
+        assert abs(s[v] - s0[v]) <= rel_mom * mom, (v, s[v], s0[v], mom)
 
 
 @pytest.mark.parametrize("scheme,cfl", [(0, 0.3), (1, 0.3), (2, 0.5)])
-def test_kelvin_helmholtz_100_steps(scheme, cfl):
+def test_kelvin_helmholtz_64_100_steps(scheme, cfl):
     from paper_1103_3373_amd import hydro as H
-    gamma = 1.4
-    box = W.kelvin_helmholtz_box(N, gamma=gamma)
+    n = 64
+    box = W.kelvin_helmholtz_box(n, gamma=GAMMA)
     grp = W.box_to_groups(box)
-    kw = dict(dh=1.0 / N, gamma=gamma, scheme=scheme, recon=H.PPM, riemann=H.HLLC, char=True)
+    kw = dict(dh=1.0 / n, gamma=GAMMA, scheme=scheme, recon=H.PPM, riemann=H.HLLC, char=True)
     s64 = torch.from_numpy(grp).cuda()
     s32 = torch.from_numpy(grp.astype(np.float32)).cuda()
     o64, o32 = torch.empty_like(s64), torch.empty_like(s32)
     dt_dev = torch.empty(1, dtype=torch.float64, device="cuda")
-    sums0 = H.conserved_sums(s64, 1.0 / N).cpu().numpy()
+    sums0 = H.conserved_sums(s64, 1.0 / n).cpu().numpy()
     ref = box.copy()
     for _ in range(STEPS):
-        dt = O.cfl_dt(ref, 1.0 / N, gamma, cfl)
-        ref = O.step_box(ref, dt, 1.0 / N, gamma, scheme, 1, 1, 1, O.F_CHAR)
+        dt = O.cfl_dt(ref, 1.0 / n, GAMMA, cfl)
+        ref = O.step_box(ref, dt, 1.0 / n, GAMMA, scheme, O.PPM, O.HLLC, O.VANLEER, O.F_CHAR)
         dt_dev.fill_(dt)
-        H.step_box(s64, o64, (N, N, N), dt_dev, **kw)
-        H.step_box(s32, o32, (N, N, N), dt_dev, **kw)
+        H.step_box(s64, o64, (n, n, n), dt_dev, **kw)
+        H.step_box(s32, o32, (n, n, n), dt_dev, **kw)
         s64, o64 = o64, s64
         s32, o32 = o32, s32
     torch.cuda.synchronize()
     refg = W.box_to_groups(ref)
-    e32 = field_errors(s32.cpu().numpy(), refg)[0]
-    e64 = field_errors(s64.cpu().numpy(), refg)[0]
-    print(f"scheme {scheme}: FP32 rel L1 {e32}, FP64 rel L1 {e64}")
-    assert e32.max() <= 1e-5, e32
-    assert e64.max() <= 1e-12, e64
-    s64n = H.conserved_sums(s64, 1.0 / N).cpu().numpy()
-    s32n = H.conserved_sums(s32, 1.0 / N).cpu().numpy()
-    for v in (0, 1, 4):
-        assert abs(s64n[v] - sums0[v]) <= 1e-13 * abs(sums0[v])
-        assert abs(s32n[v] - sums0[v]) <= 1e-6 * abs(sums0[v])
-    mom = np.sqrt((grp[:, 1:4] ** 2).sum(1)).sum() / N ** 3  # integral of |m|
-    for v in (1, 2, 3):
-        assert abs(s64n[v] - sums0[v]) <= 1e-13 * mom
-        assert abs(s32n[v] - sums0[v]) <= 1e-6 * mom
+    l1_32, li_32 = field_errors(s32.cpu().numpy(), refg)
+    l1_64, li_64 = field_errors(s64.cpu().numpy(), refg)
+    print(f"scheme {scheme}: FP32 L1 {l1_32} Linf {li_32}; FP64 L1 {l1_64} Linf {li_64}")
+    assert l1_32.max() <= 1e-5 and li_32.max() <= 1e-5, (l1_32, li_32)
+    assert l1_64.max() <= 1e-12 and li_64.max() <= 1e-12, (l1_64, li_64)
+    mom = np.sqrt((grp[:, 1:4] ** 2).sum(1)).sum() / n ** 3  # integral of |m|
+    _drift_ok(H.conserved_sums(s64, 1.0 / n).cpu().numpy(), sums0, mom, 1e-13, 1e-13)
+    _drift_ok(H.conserved_sums(s32, 1.0 / n).cpu().numpy(), sums0, mom, 1e-6, 1e-6)
+
+
+def test_kelvin_helmholtz_512_fp32_vs_fp64_on_gpu():
+    from paper_1103_3373_amd import hydro as H
+    n = 512
+    kw = dict(dh=1.0 / n, gamma=GAMMA, scheme=H.CTU, recon=H.PPM, riemann=H.HLLC, char=True)
+    s64 = torch.from_numpy(W.box_to_groups(W.kelvin_helmholtz_box(n, gamma=GAMMA))).cuda()
+    s32 = s64.float()
+    o64, o32 = torch.empty_like(s64), torch.empty_like(s32)
+    mom = (torch.sqrt((s64[:, 1:4] ** 2).sum(1)).sum() / n ** 3).item()
+    dt_dev = torch.empty(1, dtype=torch.float64, device="cuda")
+    sums0 = H.conserved_sums(s64, 1.0 / n).cpu().numpy()
+    for _ in range(STEPS):
+        H.cfl_dt(s64, 1.0 / n, GAMMA, 0.5, dt_out=dt_dev)
+        H.step_box(s64, o64, (n, n, n), dt_dev, **kw)
+        H.step_box(s32, o32, (n, n, n), dt_dev, **kw)
+        s64, o64 = o64, s64
+        s32, o32 = o32, s32
+    torch.cuda.synchronize()
+    del o64, o32
+    mag = torch.sqrt((s64[:, 1:4] ** 2).sum(1))
+    l1, li = [], []
+    for v in range(5):
+        d = (s32[:, v].double() - s64[:, v]).abs()
+        sc = mag if 1 <= v <= 3 else s64[:, v].abs()
+        l1.append((d.sum() / sc.sum()).item())
+        li.append((d.max() / sc.max()).item())
+    del mag
+    print(f"512^3 CTU FP32 vs FP64: L1 {l1} Linf {li}")
+    assert max(l1) <= 1e-5 and max(li) <= 1e-5, (l1, li)
+    _drift_ok(H.conserved_sums(s64, 1.0 / n).cpu().numpy(), sums0, mom, 1e-13, 1e-13)
+    _drift_ok(H.conserved_sums(s32, 1.0 / n).cpu().numpy(), sums0, mom, 1e-6, 1e-6)
