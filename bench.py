@@ -69,6 +69,8 @@ def parse():
     p.add_argument("--extra-reps", type=int, default=10,
                    help="launches per side measurement (groups API, other schemes, copy); 0 skips them")
     p.add_argument("--no-autotune", action="store_true", help="skip the launch-shape autotuner")
+    p.add_argument("--launch-shape", default=None, metavar="GRID,VARIANT,ZRUN",
+                   help="pin the solver's launch shape instead of autotuning (hydro_set_launch_shape)")
     p.add_argument("--graph-replays", type=int, default=10, help="replays of a captured ten-step HIP graph")
     p.add_argument("--serve", action="store_true",
                    help="run the serving workload instead (Poisson arrivals, continuous batching)")
@@ -465,9 +467,15 @@ def main():
     sums = torch.empty(5, dtype=torch.float64, device=dev)
     spec = H.make_spec(H.CTU, H.PPM, H.HLLC, H.VANLEER, gamma=gamma, char=True)
     tuned = None
-    if not args.no_autotune:
+    if args.launch_shape:
+        gr, var, zr = (int(v) for v in args.launch_shape.split(","))
+        H.set_launch_shape(spec, gr, var, zr)
+        tuned = f"pinned {gr},{var},{zr}"
+    elif not args.no_autotune:
         tuned = H.autotune(spec, G)
         print(f"[bench] autotune: grid {tuned}", file=sys.stderr, flush=True)
+    shape = H.get_launch_shape(spec, (n, n, n))
+    print(f"[bench] launch shape (grid, variant, zrun): {shape}", file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream()
     solve_kw = dict(dh=dh, gamma=gamma, scheme=H.CTU, recon=H.PPM, riemann=H.HLLC, limiter=H.VANLEER, char=True)
 
@@ -619,6 +627,7 @@ def main():
         "side": extras,
         "cpu_baseline": cpu,
         "autotune_grid": tuned,
+        "launch_shape": {"grid": shape[0], "variant": shape[1], "zrun": shape[2]},
         "final_dt": final_dt,
         "final_sums": final_sums,
     }

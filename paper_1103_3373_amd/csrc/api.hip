@@ -164,8 +164,10 @@ int check_options(int scheme, int recon, int riemann, int limiter, int flags) {
 // A launch shape is the persistent grid size and the register-budget variant
 // (minimum waves per SIMD) of the fused kernel.
 struct Tune {
-  int grid;   // 0 = default (one resident wave of workgroups)
-  int waves;  // 2 or 4
+  int grid;      // 0 = default (one resident wave of workgroups)
+  int waves;     // 2 or 4
+  int zrun;      // CTU box steps: groups per z-run (0 = default)
+  int grid_box;  // CTU box steps: workgroups (0 = as grid)
 };
 std::map<std::string, Tune> g_tune;
 bool g_tune_loaded = false;
@@ -182,9 +184,11 @@ void tune_load() {
   if (!path) return;
   FILE* f = fopen(path, "r");
   if (!f) return;
-  char key[128];
-  int gr, wv;
-  while (fscanf(f, "%127s %d %d", key, &gr, &wv) == 3) g_tune[key] = Tune{gr, wv};
+  char line[256], key[128];
+  while (fgets(line, sizeof(line), f)) {
+    int gr = 0, wv = 0, zr = 0, gb = 0;
+    if (sscanf(line, "%127s %d %d %d %d", key, &gr, &wv, &zr, &gb) >= 3) g_tune[key] = Tune{gr, wv, zr, gb};
+  }
   fclose(f);
 }
 int cu_count() {
@@ -206,7 +210,7 @@ Tune tuned(int f64, int scheme, int recon, int riemann, int charlim, long long n
   // workgroups per CU over the persistent loop (about the autotuner's choice
   // for CTU on MI355X: more, shorter workgroups even out the tail); FP64 has
   // one variant only.
-  Tune t = (it != g_tune.end()) ? it->second : Tune{0, 4};
+  Tune t = (it != g_tune.end()) ? it->second : Tune{0, 4, 0, 0};
   if (f64) t.waves = 2;
   if (t.grid <= 0) t.grid = cu_count() * (t.waves == 4 ? 12 : 1);
   if (t.grid > n_groups) t.grid = (int)n_groups;
@@ -214,10 +218,33 @@ Tune tuned(int f64, int scheme, int recon, int riemann, int charlim, long long n
   return t;
 }
 
+// Launch shape of a CTU step over one periodic box of ngz groups in z
+// (n_groups in all) without flux output: the z-run length (the tuned one,
+// or the largest of 4, 2 that divides ngz and still leaves two runs per
+// resident workgroup slot; in any case the largest built length, not above
+// it, that divides ngz) and the grid over the runs.
+Tune tuned_box(int f64, int recon, int riemann, int limiter, int charlim, long long n_groups, int ngz) {
+  Tune t = tuned(f64, HYDRO_CTU, recon, riemann, charlim, n_groups);
+  int K = t.zrun;
+  if (K <= 0) {
+    const long long slots = (long long)cu_count() * (t.waves == 4 ? 2 : 1);
+    K = 1;
+    for (int k : {4, 2})
+      if (ngz % k == 0 && n_groups / k >= 2 * slots) { K = k; break; }
+  }
+  while (K > 1 && (ngz % K || !hy::ctu_zrun_built(f64, t.waves, limiter, charlim, K))) --K;
+  t.zrun = K;
+  if (t.grid_box > 0) t.grid = t.grid_box;
+  const long long items = n_groups / K;
+  if (t.grid > items) t.grid = (int)items;
+  if (t.grid < 1) t.grid = 1;
+  return t;
+}
+
 template <typename T>
 int run_fused(const hy::Seg* segs_dev, int n_segs, long long n_groups, int g, int scheme, int recon, int riemann,
               int limiter, int flags, double gamma, unsigned long long* diag, int grid, int waves, hipStream_t st,
-              void* wstar, const hy::Seg* seg0 = nullptr, double dt0 = 0.0, int wstar_box = 0) {
+              void* wstar, const hy::Seg* seg0 = nullptr, double dt0 = 0.0, int wstar_box = 0, int zrun = 1) {
   hy::FusedArgs<T> a;
   a.segs = segs_dev;
   a.n_segs = n_segs;
@@ -236,6 +263,7 @@ int run_fused(const hy::Seg* segs_dev, int n_segs, long long n_groups, int g, in
   a.dt0 = dt0;
   a.wstar = reinterpret_cast<T*>(wstar);
   a.wstar_box = wstar_box;
+  a.zrun = zrun;
   hy::FusedCfg cfg;
   cfg.grid = grid;
   cfg.waves = waves;
@@ -335,7 +363,7 @@ int hydro_solve_groups(const void* in, void* out, void* flux_out, int n_groups, 
   // Fused path: a single segment passed by value, host dt included.
   hy::Seg seg{in, out, flux_out, nullptr, 1.0, dh, 0, n_groups, 0, 0, 0, 0};
   const Tune tu = tuned(f64, scheme, reconstruction, riemann, (flags & HYDRO_CHAR) ? 1 : 0, n_groups);
-  if (int rc = ensure_vl(w, (size_t)n_groups * hy::fused_scratch_per_group(scheme, reconstruction) * esz)) return rc;
+  if (int rc = ensure_vl(w, (size_t)n_groups * hy::fused_scratch_per_group(scheme, reconstruction, 0) * esz)) return rc;
   if (f64)
     return run_fused<double>(nullptr, 1, n_groups, g, scheme, reconstruction, riemann, limiter, flags, gamma,
                              ds->diag, tu.grid, tu.waves, st, w.vl, &seg, dt);
@@ -366,11 +394,12 @@ int hydro_solve_batch(const struct hydro_seg* segs, int n_segs, long long n_grou
   const int g = ghost_width(spec->scheme, spec->reconstruction);
   const Tune tu = tuned(f64, spec->scheme, spec->reconstruction, spec->riemann, charlim, n_groups_total);
   Workspace& w = ds->ws[st];
-  if (int rc = ensure_vl(w, (size_t)n_groups_total * hy::fused_scratch_per_group(spec->scheme, spec->reconstruction) *
+  const int box_segs = (spec->flags & HYDRO_BOX_SEGS) ? 1 : 0;
+  if (int rc = ensure_vl(w, (size_t)n_groups_total *
+                                hy::fused_scratch_per_group(spec->scheme, spec->reconstruction, box_segs) *
                                 (f64 ? 8 : 4)))
     return rc;
   const hy::Seg* sd = (const hy::Seg*)segs;
-  const int box_segs = (spec->flags & HYDRO_BOX_SEGS) ? 1 : 0;
   if (f64)
     return run_fused<double>(sd, n_segs, n_groups_total, g, spec->scheme, spec->reconstruction, spec->riemann,
                              spec->limiter, spec->flags, spec->gamma, ds->diag, tu.grid, tu.waves, st, w.vl, nullptr,
@@ -410,17 +439,21 @@ int hydro_step_box(const void* box_in, void* box_out, void* flux_out, int nx, in
   if (int rc = device_state(&ds)) return rc;
   hy::Seg seg{box_in, box_out, flux_out, dt_dev, dt_scale, dh, 0, G, nx / 16, ny / 16, nz / 16, 1};
   const int g = ghost_width(scheme, reconstruction);
-  const Tune tu = tuned(f64, scheme, reconstruction, riemann, charlim, G);
+  // CTU without flux output marches through runs of z-consecutive groups.
+  const Tune tu = (scheme == HYDRO_CTU && !flux_out)
+                      ? tuned_box(f64, reconstruction, riemann, limiter, charlim, G, nz / 16)
+                      : tuned(f64, scheme, reconstruction, riemann, charlim, G);
+  const int zrun = (scheme == HYDRO_CTU && !flux_out) ? tu.zrun : 1;
   Workspace& w = ds->ws[st];
-  if (int rc = ensure_vl(w, (size_t)G * hy::fused_scratch_per_group(scheme, reconstruction) * esz)) return rc;
+  if (int rc = ensure_vl(w, (size_t)G * hy::fused_scratch_per_group(scheme, reconstruction, 1) * esz)) return rc;
   // Passed by value: the kernel reads dt through seg.dt (segs == nullptr and
   // a device dt pointer in seg0).
   // VL: the half step is computed once per cell of the box (wstar_box).
   if (f64)
     return run_fused<double>(nullptr, 1, G, g, scheme, reconstruction, riemann, limiter, flags, gamma, ds->diag,
-                             tu.grid, tu.waves, st, w.vl, &seg, -1.0, 1);
+                             tu.grid, tu.waves, st, w.vl, &seg, -1.0, 1, zrun);
   return run_fused<float>(nullptr, 1, G, g, scheme, reconstruction, riemann, limiter, flags, gamma, ds->diag, tu.grid,
-                          tu.waves, st, w.vl, &seg, -1.0, 1);
+                          tu.waves, st, w.vl, &seg, -1.0, 1, zrun);
 }
 
 int hydro_cfl_dt(const void* U, int n_groups, double dh, double gamma, double cfl, int flags, double* dt_out,
@@ -701,7 +734,7 @@ int hydro_get_diag(struct hydro_diag* out, int reset, void* stream) {
   return 0;
 }
 
-int hydro_set_launch_shape(const struct hydro_spec* spec, int grid, int variant) {
+int hydro_set_launch_shape(const struct hydro_spec* spec, int grid, int variant, int zrun) {
   g_err[0] = 0;
   if (!spec) return fail(HYDRO_EINVAL, "null spec");
   if (int rc = check_options(spec->scheme, spec->reconstruction, spec->riemann, spec->limiter, spec->flags)) return rc;
@@ -709,10 +742,31 @@ int hydro_set_launch_shape(const struct hydro_spec* spec, int grid, int variant)
   if (grid < 0) return fail(HYDRO_EINVAL, "grid %d < 0", grid);
   if (variant != 2 && variant != 4) return fail(HYDRO_EINVAL, "variant %d not in {2, 4}", variant);
   if (f64 && variant != 2) return fail(HYDRO_EINVAL, "FP64 kernels have variant 2 only");
+  if (zrun < 0 || zrun > 64) return fail(HYDRO_EINVAL, "zrun %d not in 0..64", zrun);
   const int charlim = (spec->flags & HYDRO_CHAR) ? 1 : 0;
   std::lock_guard<std::mutex> lock(g_mu);
   tune_load();
-  g_tune[tune_key(f64, spec->scheme, spec->reconstruction, spec->riemann, charlim)] = Tune{grid, variant};
+  g_tune[tune_key(f64, spec->scheme, spec->reconstruction, spec->riemann, charlim)] = Tune{grid, variant, zrun, grid};
+  return 0;
+}
+
+int hydro_get_launch_shape(const struct hydro_spec* spec, int nx, int ny, int nz, int* grid, int* variant,
+                           int* zrun) {
+  g_err[0] = 0;
+  if (!spec || !grid || !variant || !zrun) return fail(HYDRO_EINVAL, "null pointer");
+  if (int rc = check_options(spec->scheme, spec->reconstruction, spec->riemann, spec->limiter, spec->flags)) return rc;
+  if (nx <= 0 || ny <= 0 || nz <= 0 || nx % 16 || ny % 16 || nz % 16)
+    return fail(HYDRO_EINVAL, "box sizes must be positive multiples of 16");
+  const bool f64 = (spec->flags & HYDRO_F64) != 0;
+  const int charlim = (spec->flags & HYDRO_CHAR) ? 1 : 0;
+  const long long G = (long long)(nx / 16) * (ny / 16) * (nz / 16);
+  std::lock_guard<std::mutex> lock(g_mu);
+  const Tune t = spec->scheme == HYDRO_CTU ? tuned_box(f64, spec->reconstruction, spec->riemann, spec->limiter,
+                                                       charlim, G, nz / 16)
+                                           : tuned(f64, spec->scheme, spec->reconstruction, spec->riemann, charlim, G);
+  *grid = t.grid;
+  *variant = t.waves;
+  *zrun = spec->scheme == HYDRO_CTU ? t.zrun : 1;
   return 0;
 }
 
@@ -768,7 +822,7 @@ int hydro_autotune(const struct hydro_spec* spec, int n_groups_hint, void* strea
     std::lock_guard<std::mutex> lock(g_mu);
     if (int rc = device_state(&ds)) { hipFree(in); hipFree(out); hipFree(dtd); hipFree(sd); return rc; }
     Workspace& w = ds->ws[st];
-    if (int rc = ensure_vl(w, (size_t)n * hy::fused_scratch_per_group(spec->scheme, spec->reconstruction) * esz)) {
+    if (int rc = ensure_vl(w, (size_t)n * hy::fused_scratch_per_group(spec->scheme, spec->reconstruction, 0) * esz)) {
       hipFree(in); hipFree(out); hipFree(dtd); hipFree(sd);
       return rc;
     }
@@ -777,7 +831,7 @@ int hydro_autotune(const struct hydro_spec* spec, int n_groups_hint, void* strea
   // Candidates: register variant x persistent grid (multiples of the CU count).
   const int mults[] = {1, 2, 3, 4, 6, 8, 12, 16};
   const int variants[] = {2, 4};
-  Tune best{-1, 2};
+  Tune best{-1, 2, 0, 0};
   float best_ms = 1e30f;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (e == hipSuccess) e = hipEventCreate(&e0);
@@ -802,8 +856,59 @@ int hydro_autotune(const struct hydro_spec* spec, int n_groups_hint, void* strea
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
         if (rep > 0 && ms < ms_min) ms_min = ms;  // the first launch is a warm-up
       }
-      if (ms_min < best_ms) { best_ms = ms_min; best = Tune{(int)grid, wv}; }
+      if (ms_min < best_ms) { best_ms = ms_min; best = Tune{(int)grid, wv, 0, 0}; }
       if (grid == n) break;
+    }
+  }
+  // CTU box steps: tile depth (z-run length) x grid, with the register
+  // variant just chosen, on a synthetic periodic box of the same number of
+  // groups (ngz and ngy the largest powers of two up to 16 that divide it).
+  if (e == hipSuccess && best.grid > 0 && spec->scheme == HYDRO_CTU) {
+    int ngz = 1, ngy = 1;
+    while (ngz < 16 && n % (2 * ngz) == 0) ngz *= 2;
+    while (ngy < 16 && (n / ngz) % (2 * ngy) == 0) ngy *= 2;
+    const long long ngx = n / ngz / ngy;
+    {
+      std::vector<char> host((size_t)5 * 4096 * esz);
+      for (size_t q = 0; q < 4096; ++q) {
+        double v[5] = {1.0, 0.0, 0.0, 0.0, 1.0 / (spec->gamma - 1.0)};
+        for (int k = 0; k < 5; ++k) {
+          if (f64) ((double*)host.data())[k * 4096 + q] = v[k];
+          else ((float*)host.data())[k * 4096 + q] = (float)v[k];
+        }
+      }
+      for (long long q = 0; q < n && e == hipSuccess; ++q)
+        e = hipMemcpyAsync((char*)in + q * host.size(), host.data(), host.size(), hipMemcpyHostToDevice, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
+    hy::Seg bs{in, out, nullptr, dtd, 1.0, 1.0 / 256, 0, n, (int)ngx, ngy, ngz, 1};
+    float best_box = 1e30f;
+    for (int zr : {1, 2, 4}) {
+      if (ngz % zr || e != hipSuccess) continue;
+      if (!hy::ctu_zrun_built(f64, best.waves, spec->limiter, charlim, zr)) continue;
+      const long long items = n / zr;
+      for (int m : mults) {
+        long long grid = (long long)cus * m;
+        if (grid > items) grid = items;
+        float ms_min = 1e30f;
+        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+          e = hipEventRecord(e0, st);
+          int rc = f64 ? run_fused<double>(nullptr, 1, n, g, spec->scheme, spec->reconstruction, spec->riemann,
+                                           spec->limiter, spec->flags, spec->gamma, ds->diag, (int)grid, best.waves,
+                                           st, vl, &bs, -1.0, 1, zr)
+                       : run_fused<float>(nullptr, 1, n, g, spec->scheme, spec->reconstruction, spec->riemann,
+                                          spec->limiter, spec->flags, spec->gamma, ds->diag, (int)grid, best.waves,
+                                          st, vl, &bs, -1.0, 1, zr);
+          if (rc) { e = hipErrorLaunchFailure; break; }
+          if (e == hipSuccess) e = hipEventRecord(e1, st);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          float ms = 0;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+          if (rep > 0 && ms < ms_min) ms_min = ms;
+        }
+        if (ms_min < best_box) { best_box = ms_min; best.zrun = zr; best.grid_box = (int)grid; }
+        if (grid == items) break;
+      }
     }
   }
   if (e0) hipEventDestroy(e0);
@@ -816,7 +921,7 @@ int hydro_autotune(const struct hydro_spec* spec, int n_groups_hint, void* strea
   g_tune[key] = best;
   if (const char* path = getenv("HYDRO_TUNE_CACHE")) {
     if (FILE* f = fopen(path, "a")) {
-      fprintf(f, "%s %d %d\n", key.c_str(), best.grid, best.waves);
+      fprintf(f, "%s %d %d %d %d\n", key.c_str(), best.grid, best.waves, best.zrun, best.grid_box);
       fclose(f);
     }
   }

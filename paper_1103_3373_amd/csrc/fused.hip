@@ -19,8 +19,9 @@ bool fused_supported(int scheme, int recon, int riemann, int charlim) {
   return scheme >= 0 && scheme <= 2 && (recon == 0 || recon == 1) && riemann >= 0 && riemann <= 2;
 }
 
-long long fused_scratch_per_group(int scheme, int recon) {
+long long fused_scratch_per_group(int scheme, int recon, int box_segs) {
   if (scheme != 1) return 0;
+  if (box_segs) return 5 * 4096;  // half step of the interiors, grouped like the box
   const long long n = 16 + 2 * (recon == 1 ? 3 : 2);
   return 5 * n * n * n;
 }

@@ -29,8 +29,10 @@
 //    of plane t-1 completes in plane t once its upper z flux exists.
 //  * The correction of a face state is done by the task that solves that
 //    face, so each corrected state is formed exactly once.
-// Global memory sees only the input (read once per cell), the output and
-// the optional face fluxes.
+// Global memory sees the input (each group's cells plus, from the
+// neighbouring groups, its ghost layers: about 2.4x the interior for g = 3,
+// mostly served from L2), the output, the optional face fluxes, and the
+// register spills of the two-workgroups-per-CU variant.
 #pragma once
 
 #include "fused_common.hpp"
@@ -100,7 +102,10 @@ template <typename T> HY_DEV V5<T> other_frame_d(const V5<T>& v, bool d) {
 // characteristic variables) is compiled with those two choices fixed, so the
 // limiter takes no run-time branch per component (about 10% of the kernel);
 // every other combination runs the same code with run-time choices.
-template <typename T, bool PPM, int RS, int WAVES, bool FAST>
+//
+// ZR: groups per work item (tile depth 16 * ZR): ZR > 1 only for a single
+// periodic box without flux output (a.zrun == ZR).
+template <typename T, bool PPM, int RS, int WAVES, bool FAST, int ZR>
 __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T> a) {
   constexpr int NT = kThreads;
   constexpr int G = PPM ? 3 : 2;
@@ -140,14 +145,25 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
   constexpr int nS = wS * 18;
   constexpr int nE = 19 * 18;
 
+  // Work items: single groups, or runs of ZR z-consecutive groups of one
+  // periodic box (flux output off), marched through in one pass: the z
+  // prologue and the two planes beyond each end are paid once per run.
+  constexpr int nzt = 16 * ZR;  // interior planes of an item
   int seg = 0;
-  const GroupOrder order = group_order(a.n_groups);
-  for (long long grp = order.first; grp < order.end; grp += order.stride) {
+  const GroupOrder order = group_order(a.n_groups / ZR);
+  for (long long item = order.first; item < order.end; item += order.stride) {
     double dt;
-    const Seg* S = find_seg(a, grp, seg, dt);
-    const long long lg = grp - S->first;
+    const Seg* S = find_seg(a, item * ZR, seg, dt);
+    long long lg = item * ZR - S->first;  // the item's first group (local)
+    int gzs = 0;                           // groups between z neighbours
+    if constexpr (ZR > 1) {
+      // item -> (column c, run r) of the box; group (r ZR + j) nxy + c
+      const int nxy = S->ngx * S->ngy, li = (int)(item - S->first / ZR);
+      lg = (long long)(li / nxy) * ZR * nxy + li % nxy;
+      gzs = nxy;
+    }
     T* __restrict__ O = reinterpret_cast<T*>(S->out) + lg * 5 * 4096;
-    T* __restrict__ FO = S->flux ? reinterpret_cast<T*>(S->flux) + lg * 3 * a.nf * 5 * 256 : nullptr;
+    T* __restrict__ FO = (ZR == 1 && S->flux) ? reinterpret_cast<T*>(S->flux) + lg * 3 * a.nf * 5 * 256 : nullptr;
     ph.dtdh = (T)(dt / S->dh);
     ph.hdtdh = (T)(0.5 * dt / S->dh);
     // The group's cells (ghosts included) come from the ghosted input or, in
@@ -199,14 +215,14 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
       tally.floors(floor_state(ztm, ph) + floor_state(ztp, ph));
     }
 
-    for (int t = -1; t <= 16; ++t) {
+    for (int t = -1; t <= nzt; ++t) {
       // ---- A: columns: primitive plane t; trace plane t+1; H1(t+1/2) -------
       V5<T> nzm, nzp;  // traced states of plane t+1
       if (col.cross) {
         const V5<T> wl = from_frame<2>(w0);
         sts5(sP, kP, pcol, wl);
         sts5(sQ, kP, qcol, to_frame<1>(wl));
-        if (t <= 15) {
+        if (t < nzt) {
           if (PPM) {
             V5<T> w3 = zprim(t + 3);
             V5<T> s2 = slope(w1, w2, w3, ph);
@@ -336,7 +352,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
         tally.fails(nf);
         zcp = cp;
       }
-      if (t >= 0 && t <= 15) {
+      if (t >= 0 && t < nzt) {
         for (int q = NT - 1 - tid; q < 2 * kF2; q += NT) {
           const bool d = q >= kF2;
           const int r = d ? q - kF2 : q;
@@ -371,11 +387,14 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
         const int x = col.x, y = col.y;
         if (t >= 1) {
           V5<T> u = load_cons(t - 1);
-          const int o = ((t - 1) * 16 + y) * 16 + x;
+          // plane t-1 lies in the item's group (t-1)/16, at its z = (t-1)%16
+          T* Og = O;
+          if constexpr (ZR > 1) Og += (long)((t - 1) >> 4) * gzs * (5 * 4096);
+          const int o = (((t - 1) & 15) * 16 + y) * 16 + x;
 #pragma unroll
-          for (int n = 0; n < 5; ++n) O[n * 4096 + o] = u[n] - ph.dtdh * (acc[n] + hn[n]);
+          for (int n = 0; n < 5; ++n) Og[n * 4096 + o] = u[n] - ph.dtdh * (acc[n] + hn[n]);
         }
-        if (t >= 0 && t <= 15) {
+        if (t >= 0 && t < nzt) {
           V5<T> fx = sub5(lds5(sF2, kF2, y * 17 + x + 1), lds5(sF2, kF2, y * 17 + x));
           V5<T> gy = from_frame<1>(sub5(lds5(sF2 + 5 * kF2, kF2, x * 17 + y + 1), lds5(sF2 + 5 * kF2, kF2, x * 17 + y)));
 #pragma unroll
@@ -388,7 +407,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
             for (int n = 0; n < 5; ++n) FO[((2 * a.nf + f) * 5 + n) * 256 + y * 16 + x] = hn[n];
           }
         }
-      } else if (FO && t >= 0 && t <= 15) {
+      } else if (FO && t >= 0 && t < nzt) {
         const int q = tid - 256;
         if (q < 2 * a.nf * 16) {
           const bool d = q >= a.nf * 16;

@@ -7,15 +7,25 @@ namespace hy {
 
 hipError_t launch_ctu_f32_roe(const FusedArgs<float>& a, int recon, int waves, bool fast, int grid, hipStream_t st);
 
-template <bool PPM, int RS, int WAVES, bool FAST>
-static hipError_t launch_one(const FusedArgs<float>& a, int grid, hipStream_t st) {
-  auto k = ctu::ctu_fused_kernel<float, PPM, RS, WAVES, FAST>;
+template <bool PPM, int RS, int WAVES, bool FAST, int ZR>
+static hipError_t launch_zr(const FusedArgs<float>& a, int grid, hipStream_t st) {
+  auto k = ctu::ctu_fused_kernel<float, PPM, RS, WAVES, FAST, ZR>;
   const size_t shm = ctu::kLdsBytes(sizeof(float));
   static std::atomic<unsigned long long> lds_set{0};
   const hipError_t e = raise_lds_limit((const void*)k, shm, lds_set);
   if (e != hipSuccess) return e;
   k<<<dim3(grid), dim3(ctu::kThreads), shm, st>>>(a);
   return hipGetLastError();
+}
+
+template <bool PPM, int RS, int WAVES, bool FAST>
+static hipError_t launch_one(const FusedArgs<float>& a, int grid, hipStream_t st) {
+  if constexpr (WAVES == 4 && FAST) {
+    if (a.zrun == 2) return launch_zr<PPM, RS, WAVES, FAST, 2>(a, grid, st);
+    if (a.zrun == 4) return launch_zr<PPM, RS, WAVES, FAST, 4>(a, grid, st);
+  }
+  if (a.zrun != 1) return hipErrorInvalidValue;
+  return launch_zr<PPM, RS, WAVES, FAST, 1>(a, grid, st);
 }
 
 template <int WAVES, bool FAST>

@@ -5,7 +5,8 @@ namespace hy {
 
 template <bool PPM, int RS, int WAVES, bool FAST>
 static hipError_t launch_one(const FusedArgs<double>& a, int grid, hipStream_t st) {
-  auto k = ctu::ctu_fused_kernel<double, PPM, RS, WAVES, FAST>;
+  if (a.zrun != 1) return hipErrorInvalidValue;  // one tile depth in FP64
+  auto k = ctu::ctu_fused_kernel<double, PPM, RS, WAVES, FAST, 1>;
   const size_t shm = ctu::kLdsBytes(sizeof(double));
   static std::atomic<unsigned long long> lds_set{0};
   const hipError_t e = raise_lds_limit((const void*)k, shm, lds_set);

@@ -77,7 +77,20 @@ struct FusedArgs {
   // box of its own whose ghost cells the second stage reads from neighbours.
   T* wstar;
   int wstar_box;
+  // CTU on one periodic box (seg0, no flux output): a workgroup marches
+  // through zrun z-consecutive groups of one (gx, gy) column in one pass, so
+  // the work items are n_groups / zrun runs (ngz a multiple of zrun).  1
+  // everywhere else.
+  int zrun;
 };
+
+// Tile depths (groups per z-run) built for the CTU kernel: 1 always; 2 and
+// 4 for the FP32 specialization of the production configuration (van Leer
+// limiter on characteristic variables) with two workgroups per CU.
+inline bool ctu_zrun_built(bool f64, int waves, int limiter, int charlim, int zrun) {
+  if (zrun == 1) return true;
+  return !f64 && waves == 4 && limiter == 1 && charlim == 1 && (zrun == 2 || zrun == 4);
+}
 
 struct FusedCfg {
   int grid;          // number of workgroups (persistent)
@@ -85,8 +98,10 @@ struct FusedCfg {
 };
 
 bool fused_supported(int scheme, int recon, int riemann, int charlim);
-// Elements of T per group of the VL half-step scratch (0 for other schemes).
-long long fused_scratch_per_group(int scheme, int recon);
+// Elements of T per group of the VL half-step scratch (0 for other schemes):
+// the ghosted half-step region of a group, or with box_segs (every segment a
+// periodic box) only its interior.
+long long fused_scratch_per_group(int scheme, int recon, int box_segs);
 hipError_t launch_fused(const FusedArgs<float>& a, int scheme, int recon, int riemann, const FusedCfg& cfg,
                         hipStream_t st);
 hipError_t launch_fused(const FusedArgs<double>& a, int scheme, int recon, int riemann, const FusedCfg& cfg,

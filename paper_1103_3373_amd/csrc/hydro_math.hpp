@@ -45,6 +45,10 @@ HY_DEV float vsign_of(float m, float s) { return __builtin_copysignf(m, s); }
 HY_DEV double vsign_of(double m, double s) { return __builtin_copysign(m, s); }
 HY_DEV float vabs(float a) { return __builtin_fabsf(a); }
 HY_DEV double vabs(double a) { return __builtin_fabs(a); }
+// Median of three: one v_med3_f32 in FP32; FP64 (no such instruction)
+// composes it from min and max.
+HY_DEV float vmed3(float a, float b, float c) { return __builtin_amdgcn_fmed3f(a, b, c); }
+HY_DEV double vmed3(double a, double b, double c) { return vmax(vmin(a, b), vmin(vmax(a, b), c)); }
 // FP32 uses the hardware reciprocal and square root (about 1 ulp) instead
 // of the multi-instruction correctly rounded sequences; FP64 stays IEEE.
 HY_DEV float vsqrt(float a) { return __builtin_amdgcn_sqrtf(a); }
@@ -205,7 +209,7 @@ HY_DEV V5<T> slope(const V5<T>& wm, const V5<T>& w0, const V5<T>& wp, const Phys
 }
 
 // PPM edge between cells a and b (states, limited slopes), clipped into the
-// range of the two cell values.
+// range of the two cell values: the median of the edge and the two values.
 template <typename T>
 HY_DEV V5<T> ppm_edge(const V5<T>& wa, const V5<T>& wb, const V5<T>& sa, const V5<T>& sb) {
   V5<T> e;
@@ -213,28 +217,29 @@ HY_DEV V5<T> ppm_edge(const V5<T>& wa, const V5<T>& wb, const V5<T>& sa, const V
 #pragma unroll
   for (int n = 0; n < 5; ++n) {
     T v = T(0.5) * (wa[n] + wb[n]) - (sb[n] - sa[n]) * sixth;
-    e[n] = vmin(vmax(v, vmin(wa[n], wb[n])), vmax(wa[n], wb[n]));
+    e[n] = vmed3(v, wa[n], wb[n]);
   }
   return e;
 }
 
-// Parabola monotonization per component.
+// Parabola monotonization per component, in median form.  For a cell value
+// a with edges l and r the three cases of the monotonization are:
+//   local extremum ((r - a)(a - l) <= 0): both edges become a;
+//   the left edge overshoots (the parabola has an extremum inside the cell
+//     next to l): l becomes 3a - 2r; likewise r becomes 3a - 2l;
+//   otherwise the edges stay.
+// With dl = a - l and dr = r - a of one sign, the overshoot test
+// 6 (r - l)(a - (l + r)/2) > (r - l)^2 reduces to |dl| > 2|dr|, and all
+// three cases are l = med3(l, a, 3a - 2r), r = med3(r, a, 3a - 2l): a lies
+// between the other two exactly at an extremum, and otherwise the median
+// picks the edge or its replacement, whichever is nearer to a.  The forms
+// coincide at every switching point.
 template <typename T> HY_DEV void ppm_mono(const V5<T>& w, V5<T>& wl, V5<T>& wr) {
-  const T sixth = T(1) / T(6);
 #pragma unroll
   for (int n = 0; n < 5; ++n) {
-    const T a = w[n], l = wl[n], r = wr[n];
-    // The two overshoot cases exclude each other (d2 >= 0), so both
-    // replacements are formed from the unmodified edges and selected.
-    const bool ext = (r - a) * (a - l) <= T(0);
-    const T d = r - l;
-    const T t = d * (a - T(0.5) * (l + r));
-    const T d2 = d * d * sixth;
-    const T a3 = T(3) * a;
-    const T nl = t > d2 ? a3 - T(2) * r : l;
-    const T nr = t < -d2 ? a3 - T(2) * l : r;
-    wl[n] = ext ? a : nl;
-    wr[n] = ext ? a : nr;
+    const T a = w[n], a3 = T(3) * a, l = wl[n], r = wr[n];
+    wl[n] = vmed3(l, a, a3 - T(2) * r);
+    wr[n] = vmed3(r, a, a3 - T(2) * l);
   }
 }
 
@@ -251,8 +256,8 @@ HY_DEV void plm_faces(const V5<T>& wm, const V5<T>& w, const V5<T>& wp, const V5
   if (ph.charlim) {
 #pragma unroll
     for (int n = 0; n < 5; ++n) {
-      fl[n] = vmin(vmax(fl[n], vmin(w[n], wm[n])), vmax(w[n], wm[n]));
-      fr[n] = vmin(vmax(fr[n], vmin(w[n], wp[n])), vmax(w[n], wp[n]));
+      fl[n] = vmed3(fl[n], w[n], wm[n]);
+      fr[n] = vmed3(fr[n], w[n], wp[n]);
     }
   }
 }

@@ -27,7 +27,7 @@ EXPORTS = (
     "hydro_ghost_width", "hydro_solve_groups", "hydro_cfl_dt", "hydro_conserved_sums", "hydro_cfl_dt_sums",
     "hydro_fill_ghosts_periodic", "hydro_fill_groups_interp", "hydro_group_map_len", "hydro_build_group_map",
     "hydro_fill_groups_amr", "hydro_amr_correct", "hydro_accumulate", "hydro_solve_batch", "hydro_autotune",
-    "hydro_set_launch_shape", "hydro_step_box", "hydro_cfl_dt_batch", "hydro_cfl_dt_batch_noalloc",
+    "hydro_set_launch_shape", "hydro_get_launch_shape", "hydro_step_box", "hydro_cfl_dt_batch", "hydro_cfl_dt_batch_noalloc",
     "hydro_get_diag", "hydro_last_error", "hydro_shutdown",
 )
 
@@ -100,8 +100,10 @@ def lib() -> ctypes.CDLL:
     L.hydro_solve_batch.restype = i
     L.hydro_autotune.argtypes = [ctypes.POINTER(Spec), i, P]
     L.hydro_autotune.restype = i
-    L.hydro_set_launch_shape.argtypes = [ctypes.POINTER(Spec), i, i]
+    L.hydro_set_launch_shape.argtypes = [ctypes.POINTER(Spec), i, i, i]
     L.hydro_set_launch_shape.restype = i
+    L.hydro_get_launch_shape.argtypes = [ctypes.POINTER(Spec), i, i, i, P, P, P]
+    L.hydro_get_launch_shape.restype = i
     L.hydro_get_diag.argtypes = [ctypes.POINTER(Diag), i, P]
     L.hydro_get_diag.restype = i
     L.hydro_last_error.argtypes = []
@@ -377,10 +379,22 @@ def autotune(spec: Spec, n_groups_hint: int, stream=None) -> int:
     return _check("hydro_autotune", lib().hydro_autotune(ctypes.byref(spec), int(n_groups_hint), _stream(stream)))
 
 
-def set_launch_shape(spec: Spec, grid: int, variant: int) -> None:
+def set_launch_shape(spec: Spec, grid: int, variant: int, zrun: int = 0) -> None:
     """Pin the fused kernel's launch shape for spec's specialization
-    (grid 0 = default; variant 2 or 4, see hydro_set_launch_shape)."""
-    _check("hydro_set_launch_shape", lib().hydro_set_launch_shape(ctypes.byref(spec), int(grid), int(variant)))
+    (grid 0 = default; variant 2 or 4; zrun = groups per z-run of a CTU box
+    step, 0 = default; see hydro_set_launch_shape)."""
+    _check("hydro_set_launch_shape", lib().hydro_set_launch_shape(ctypes.byref(spec), int(grid), int(variant),
+                                                                  int(zrun)))
+
+
+def get_launch_shape(spec: Spec, shape) -> tuple:
+    """(grid, variant, zrun) that step_box uses for spec on a box of
+    shape = (nx, ny, nz) without flux output."""
+    a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    nx, ny, nz = shape
+    _check("hydro_get_launch_shape", lib().hydro_get_launch_shape(ctypes.byref(spec), int(nx), int(ny), int(nz),
+                                                                  ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
 
 
 def get_diag(reset=False, stream=None) -> dict:

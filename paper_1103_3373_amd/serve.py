@@ -56,10 +56,13 @@ class Sim:
 
 
 def footprint_bytes(req: Request) -> int:
-    """Device bytes held by a simulation: two state buffers, plus its share
-    of the VL half-step scratch (ghosted W*, (22/16)^3 of the state)."""
+    """Device bytes held by a simulation: two state buffers, plus for VL its
+    share of the library's half-step scratch.  Every simulation is a
+    periodic-box segment, so that scratch holds the half step of the
+    interiors only: one more state-sized buffer per VL simulation of the
+    batched launch."""
     state = (req.n ** 3) * 20
-    extra = int(state * (22 ** 3) / (16 ** 3)) if req.scheme == 1 else 0
+    extra = state if req.scheme == 1 else 0
     return 2 * state + extra
 
 

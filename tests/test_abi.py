@@ -101,13 +101,14 @@ def test_set_launch_shape_validation():
     ctu = H.make_spec(H.CTU, H.PPM, H.HLLC, gamma=1.4, char=True)
     mhm = H.make_spec(H.MHM, H.PPM, H.HLLC, gamma=1.4, char=True)
     f64 = H.make_spec(H.CTU, H.PPM, H.HLLC, gamma=1.4, char=True, f64=True)
-    for bad in ((ctu, 0, 1), (ctu, 0, 3), (ctu, 0, 5), (ctu, -1, 2), (mhm, 0, 3), (f64, 0, 4)):
+    for bad in ((ctu, 0, 1), (ctu, 0, 3), (ctu, 0, 5), (ctu, -1, 2), (mhm, 0, 3), (f64, 0, 4), (ctu, 0, 4, -1),
+                (ctu, 0, 4, 65)):
         with pytest.raises(H.HydroError):
             H.set_launch_shape(*bad)
     H.set_launch_shape(mhm, 0, 4)
     H.set_launch_shape(f64, 512, 2)
-    H.set_launch_shape(ctu, 7, 2)
-    H.set_launch_shape(ctu, 0, 4)  # back to the default variant
+    H.set_launch_shape(ctu, 7, 2, 4)
+    H.set_launch_shape(ctu, 0, 4)  # back to the default variant and tile depth
 
 
 def test_cfl_dt_sums_validation(L):
@@ -192,3 +193,39 @@ def test_noalloc_dt_rejects_sizes_before_device_calls(L):
     assert call(1, -8) == -1
     assert call(0, 0) == 0
     assert call(1, 0) == 0
+
+
+def test_box_launch_shape_defaults_and_pins():
+    """Host logic of the CTU box step's launch shape (no device work; the
+    compute-unit count is 256 on MI355X and the library's fallback without
+    a device): the default tile depth is the largest of 4, 2 that divides
+    the box's groups in z and leaves two runs per resident workgroup slot; a
+    pinned depth that is not built or does not divide it falls back to the
+    largest built divisor below it (depths 2 and 4 exist for the FP32 van
+    Leer / characteristic specialization with two workgroups per CU only);
+    other schemes march one group at a time."""
+    from paper_1103_3373_amd import hydro as H
+    ctu = H.make_spec(H.CTU, H.PPM, H.HLLC, gamma=1.4, char=True)
+    mhm = H.make_spec(H.MHM, H.PPM, H.HLLC, gamma=1.4, char=True)
+    try:
+        H.set_launch_shape(ctu, 0, 4, 0)
+        assert H.get_launch_shape(ctu, (256, 256, 256)) == (1024, 4, 4)  # 4096 groups: 1024 runs of 4
+        assert H.get_launch_shape(ctu, (512, 512, 512)) == (3072, 4, 4)
+        assert H.get_launch_shape(ctu, (64, 64, 48))[2] == 1  # 48 groups: too few for runs
+        H.set_launch_shape(ctu, 512, 4, 8)
+        assert H.get_launch_shape(ctu, (256, 256, 256)) == (512, 4, 4)
+        H.set_launch_shape(ctu, 0, 4, 3)
+        assert H.get_launch_shape(ctu, (256, 256, 256)) == (2048, 4, 2)
+        H.set_launch_shape(ctu, 0, 2, 4)
+        assert H.get_launch_shape(ctu, (256, 256, 256)) == (256, 2, 1)
+        f64 = H.make_spec(H.CTU, H.PPM, H.HLLC, gamma=1.4, char=True, f64=True)
+        H.set_launch_shape(f64, 0, 2, 4)
+        assert H.get_launch_shape(f64, (256, 256, 256))[2] == 1
+        H.set_launch_shape(f64, 0, 2, 0)
+        minmod = H.make_spec(H.CTU, H.PPM, H.HLLC, H.GMINMOD, gamma=1.4, char=True)
+        assert H.get_launch_shape(minmod, (256, 256, 256))[2] == 1
+        assert H.get_launch_shape(mhm, (256, 256, 256))[2] == 1
+        with pytest.raises(H.HydroError):
+            H.get_launch_shape(ctu, (256, 256, 250))
+    finally:
+        H.set_launch_shape(ctu, 0, 4, 0)
