@@ -341,36 +341,41 @@ def serve_bench(args):
             for r in stream]
     cache = {}
     print(f"[serve] generating initial states", file=sys.stderr, flush=True)
-    be = GpuBackend(gamma=gamma, ic_cache=cache)
-    for ic in ("sod", "blast", "lognormal"):
-        for n in (32, 64, 128):
-            for seed in range(4):
-                be._ic(Request(0, 0.0, n, 0, 0, ic, seed))
-    # Warm-up: every specialization once at the largest size (one-time kernel
-    # attributes and scratch growth happen here, not in the timed run).
-    print(f"[serve] warm-up", file=sys.stderr, flush=True)
-    warm = Server(be)
-    k = 0
-    for s in (0, 1, 2):
-        for rs in (0, 1):
-            for _ in range(8):
-                warm.submit(Request(10 ** 6 + k, 0.0, 128, s, rs, "lognormal", 0, 2))
-                k += 1
-    warm.run()
-    torch.cuda.synchronize()
-    print(f"[serve] {len(reqs)} requests at {args.serve_rate}/s", file=sys.stderr, flush=True)
-    srv = Server(be, mem_cap=200e9)
-    for r in reqs:
-        srv.submit(r)
-    srv.run()
-    rep = srv.report()
+    reports = {}
+    for overlap in (False, True):
+        be = GpuBackend(gamma=gamma, ic_cache=cache, overlap=overlap)
+        for ic in ("sod", "blast", "lognormal"):
+            for n in (32, 64, 128):
+                for seed in range(4):
+                    be._ic(Request(0, 0.0, n, 0, 0, ic, seed))
+        # Warm-up: every specialization once at the largest size (one-time
+        # kernel attributes and scratch growth happen here, not in the timed run).
+        print(f"[serve] warm-up (overlap={overlap})", file=sys.stderr, flush=True)
+        warm = Server(be)
+        k = 0
+        for s in (0, 1, 2):
+            for rs in (0, 1):
+                for _ in range(8):
+                    warm.submit(Request(10 ** 6 + k, 0.0, 128, s, rs, "lognormal", 0, 2))
+                    k += 1
+        warm.run()
+        torch.cuda.synchronize()
+        print(f"[serve] {len(reqs)} requests at {args.serve_rate}/s (overlap={overlap})", file=sys.stderr, flush=True)
+        srv = Server(be, mem_cap=200e9)
+        for r in reqs:
+            srv.submit(r)
+        srv.run()
+        reports[overlap] = dict(srv.report(), table_uploads=be.table_builds)
+    rep = reports[True]
     offered = sum(r.n ** 3 * r.steps for r in reqs) / (reqs[-1].arrival if reqs else 1.0)
     out = {"metric": "serving: p50/p99 per-step latency and aggregate cell-updates/s", "unit": "cell-updates/s",
            "value": rep["cell_updates_per_s"], "higher_is_better": True, "n_gpus": 1, "dtype": "f32",
            "data": "synthetic (Sod / blast / lognormal seeded initial conditions)",
            "config": {"workload": f"{len(reqs)} Poisson requests, mean {args.serve_rate}/s, boxes 32^3/64^3/128^3, "
-                                  "MHM/VL/CTU x Roe/HLLC, PPM(char, van Leer), 50 steps, 200 GB cap"},
-           "offered_cell_updates_per_s": offered, **rep}
+                                  "MHM/VL/CTU x Roe/HLLC, PPM(char, van Leer), 50 steps, 200 GB cap",
+                      "backend": "one stream per scheme, resident segment tables"},
+           "offered_cell_updates_per_s": offered, **rep,
+           "single_stream": reports[False]}
     print(json.dumps(out))
 
 

@@ -7,7 +7,8 @@ as their memory footprint fits under the cap, and advances *all* active
 simulations by one step per tick: one batched launch of the fused solver per
 (scheme, solver) specialization, each simulation a box-mode segment with its
 own time step read from device memory, followed by that simulation's FP64
-CFL time step.  Requests that arrive while others are on the GPU join at the
+CFL time step.  The classes of a tick run on one stream per scheme, so their
+launches overlap on the device, and their segment tables stay resident.  Requests that arrive while others are on the GPU join at the
 next tick; finished ones retire and free their memory.  Host bookkeeping of
 the next tick overlaps the device work of the current one.
 
@@ -218,10 +219,20 @@ class HostBackend:
 
 class GpuBackend:
     """Backend on the HIP library: resident grouped boxes, batched box-mode
-    launches per (scheme, solver), per-simulation FP64 dt, device events."""
+    launches per (scheme, solver) class, per-simulation FP64 dt, device
+    events.
+
+    overlap=True (default): every simulation lives on the stream of its
+    scheme (three streams at the default priority, so the classes of one tick
+    run concurrently on the device), and each class keeps its segment tables
+    resident in device memory, one per parity of the tick (the two ping-pong
+    buffers of each simulation swap roles every step); a class's tables are
+    rebuilt only when its membership changes.  overlap=False: everything on
+    the caller's stream with a table built and uploaded per class and tick
+    (the former design, kept for comparison)."""
 
     def __init__(self, gamma=1.4, recon=None, char=True, limiter=None, cfl=None, ic_cache=None,
-                 keep_results=False):
+                 keep_results=False, overlap=True):
         import torch
         from . import hydro as H
         from . import workloads as W
@@ -237,9 +248,17 @@ class GpuBackend:
         self.keep_results = keep_results
         self.results = {}
         self.specs = {}
+        self.overlap = overlap
+        self.scheme_streams = {}
+        self.classes = {}
+        self.tick_no = 0
+        self.table_builds = 0
 
     class Handle:
-        __slots__ = ("req", "a", "b", "dt", "flip", "G")
+        __slots__ = ("req", "a", "b", "dt", "flip", "G", "stream")
+
+    class Class:
+        __slots__ = ("stream", "members", "tables", "total")
 
     def _ic(self, req):
         key = (req.ic, req.n, req.seed)
@@ -247,6 +266,13 @@ class GpuBackend:
             box = self.W.initial_box(req.ic, req.n, self.gamma, req.seed)
             self.ic_cache[key] = self.torch.from_numpy(self.W.box_to_groups(box).astype(np.float32)).pin_memory()
         return self.ic_cache[key]
+
+    def _stream_of(self, scheme):
+        if not self.overlap:
+            return self.stream
+        if scheme not in self.scheme_streams:
+            self.scheme_streams[scheme] = self.torch.cuda.Stream(device=self.dev)  # default priority
+        return self.scheme_streams[scheme]
 
     def start(self, clock, t0):
         torch = self.torch
@@ -262,18 +288,23 @@ class GpuBackend:
         h.req = req
         host = self._ic(req)
         h.G = host.shape[0]
-        h.a = torch.empty_like(host, device=self.dev)
-        h.a.copy_(host, non_blocking=True)
-        h.b = torch.empty_like(h.a)
-        h.dt = torch.empty(1, dtype=torch.float64, device=self.dev)
+        h.stream = self._stream_of(req.scheme)
+        # Buffers are allocated, filled and first used on the simulation's
+        # stream, so the allocator orders their reuse after its work.
+        with torch.cuda.stream(h.stream):
+            h.a = torch.empty_like(host, device=self.dev)
+            h.a.copy_(host, non_blocking=True)
+            h.b = torch.empty_like(h.a)
+            h.dt = torch.empty(1, dtype=torch.float64, device=self.dev)
+            self.H.cfl_dt(h.a, 1.0 / req.n, self.gamma, self.cfl[req.scheme], dt_out=h.dt, stream=h.stream)
         h.flip = False
-        self.H.cfl_dt(h.a, 1.0 / req.n, self.gamma, self.cfl[req.scheme], dt_out=h.dt)
         return h
 
     def retire(self, h):
         if self.keep_results:
-            src = h.b if h.flip else h.a
-            self.results[h.req.id] = src.cpu()
+            with self.torch.cuda.stream(h.stream):
+                src = h.b if h.flip else h.a
+                self.results[h.req.id] = src.cpu()
         h.a = h.b = None
 
     def idle_until(self, t_abs):
@@ -290,26 +321,58 @@ class GpuBackend:
                                                char=self.char, box_segs=True)
         return self.specs[key]
 
+    def _table(self, hs, swapped):
+        """Device segment table of a class: each simulation's step from its
+        current buffer into the other (swapped: the step after)."""
+        rows, first = [], 0
+        for h in hs:
+            src, dst = (h.b, h.a) if h.flip != swapped else (h.a, h.b)
+            ng = h.req.n // 16
+            rows.append((src, dst, None, h.dt, 1.0, 1.0 / h.req.n, first, h.G, (ng, ng, ng)))
+            first += h.G
+        self.table_builds += 1
+        return self.H.seg_table(rows, self.dev), first
+
     def tick(self, handles):
         torch, H = self.torch, self.H
         by_spec = {}
         for h in handles:
             by_spec.setdefault((h.req.scheme, h.req.riemann), []).append(h)
+        parity = self.tick_no & 1
+        used = []
         for (scheme, riemann), hs in by_spec.items():
-            rows, first = [], 0
-            for h in hs:
-                src, dst = (h.b, h.a) if h.flip else (h.a, h.b)
-                ng = h.req.n // 16
-                rows.append((src, dst, None, h.dt, 1.0, 1.0 / h.req.n, first, h.G, (ng, ng, ng)))
-                first += h.G
-            table = H.seg_table(rows, self.dev)
-            H.solve_batch(table, len(rows), first, self._spec(scheme, riemann))
-            # the same table: each segment's new state (`out`) -> its dt
-            H.cfl_dt_batch(table, len(rows), first, gamma=self.gamma, cfl=self.cfl[scheme])
+            cls = self.classes.get((scheme, riemann))
+            if cls is None:
+                cls = self.classes[(scheme, riemann)] = GpuBackend.Class()
+                cls.stream, cls.members, cls.tables, cls.total = self._stream_of(scheme), None, [None, None], 0
+            with torch.cuda.stream(cls.stream):
+                ids = tuple(h.req.id for h in hs)
+                if not self.overlap:
+                    table, cls.total = self._table(hs, False)
+                else:
+                    if ids != cls.members:
+                        # Every member steps every tick until its last step,
+                        # so the two tables stay valid while the membership
+                        # does: this tick's, and the next one's.
+                        cls.members = ids
+                        cls.tables[parity], cls.total = self._table(hs, False)
+                        cls.tables[1 - parity], _ = self._table(hs, True)
+                    table = cls.tables[parity]
+                H.solve_batch(table, len(hs), cls.total, self._spec(scheme, riemann), stream=cls.stream)
+                # the same table: each segment's new state (`out`) -> its dt
+                H.cfl_dt_batch(table, len(hs), cls.total, gamma=self.gamma, cfl=self.cfl[scheme], stream=cls.stream)
             for h in hs:
                 h.flip = not h.flip
+            if cls.stream not in used:
+                used.append(cls.stream)
+        for st in used:
+            if st is not self.stream:
+                ev = torch.cuda.Event()
+                ev.record(st)
+                self.stream.wait_event(ev)
         ev = torch.cuda.Event(enable_timing=True)
         ev.record(self.stream)
+        self.tick_no += 1
         return ev
 
     def wait(self, ev):

@@ -1,6 +1,8 @@
 """GPU serving: each request's final state is bit-identical alone and inside
 a mixed continuous-batching stream (different sizes, schemes, solvers and
-initial conditions sharing batched launches), and matches the FP64 oracle
+initial conditions sharing batched launches; the mix runs the classes on one
+stream per scheme with resident segment tables, the requests alone run on
+one stream with per-tick tables), and matches the FP64 oracle
 run of the same initial condition for the same number of steps, each step
 at the oracle's own CFL time step (PPM with characteristic limiting, van
 Leer, as served).
@@ -45,8 +47,12 @@ def test_results_same_alone_and_in_mix():
     assert len(srv.done) == len(reqs)
     ticks = [len(s.latencies) for s in srv.done.values()]
     assert all(t == 6 for t in ticks)
+    # Tables are rebuilt only when a class's membership changes: each request
+    # joins and leaves its class once, and a change builds two tables.
+    assert be.table_builds <= 4 * len(reqs)
     for r in reqs:
-        alone_be = GpuBackend(ic_cache=cache, keep_results=True)
+        # alone, and with the single-stream backend (a table per class and tick)
+        alone_be = GpuBackend(ic_cache=cache, keep_results=True, overlap=False)
         alone = Server(alone_be)
         alone.submit(Request(r.id, 0.0, r.n, r.scheme, r.riemann, r.ic, r.seed, r.steps))
         alone.run()
