@@ -375,6 +375,17 @@ template <typename T> HY_DEV T total_energy(const V5<T>& W, const Phys<T>& ph) {
   return W[4] * ph.inv_gm1 + T(0.5) * W[0] * (W[1] * W[1] + W[2] * W[2] + W[3] * W[3]);
 }
 
+// Physical flux of a frame state whose total energy E is known.
+template <typename T> HY_DEV V5<T> flux_with_energy(const V5<T>& W, T E) {
+  V5<T> F;
+  F[0] = W[0] * W[1];
+  F[1] = F[0] * W[1] + W[4];
+  F[2] = F[0] * W[2];
+  F[3] = F[0] * W[3];
+  F[4] = W[1] * (E + W[4]);
+  return F;
+}
+
 template <typename T>
 HY_DEV V5<T> hlle(const V5<T>& L, const V5<T>& R, const Phys<T>& ph) {
   T EL = total_energy(L, ph), ER = total_energy(R, ph);
@@ -385,7 +396,7 @@ HY_DEV V5<T> hlle(const V5<T>& L, const V5<T>& R, const Phys<T>& ph) {
   T SR = vmax(R[1] + cR, a.u + ct);
   T bm = vmin(SL, T(0)), bp = vmax(SR, T(0));
   T idb = vrcp(bp - bm);
-  V5<T> FL = flux_of(L, ph), FR = flux_of(R, ph);
+  V5<T> FL = flux_with_energy(L, EL), FR = flux_with_energy(R, ER);
   V5<T> UL, UR;
   UL[0] = L[0]; UL[1] = L[0] * L[1]; UL[2] = L[0] * L[2]; UL[3] = L[0] * L[3]; UL[4] = EL;
   UR[0] = R[0]; UR[1] = R[0] * R[1]; UR[2] = R[0] * R[2]; UR[3] = R[0] * R[3]; UR[4] = ER;
@@ -416,22 +427,42 @@ HY_DEV V5<T> hllc(const V5<T>& L, const V5<T>& R, const Phys<T>& ph) {
   T S = left ? SL : SR;
   T m = left ? mL : mR;
   T rs = left ? a.rL : a.rR;
-  V5<T> F = flux_of(W, ph);
+  V5<T> F = flux_with_energy(W, E);
   if (supL || supR) return F;
-  T fac = vdiv(m, S - Ss);
-  V5<T> U;
-  U[0] = W[0]; U[1] = W[0] * W[1]; U[2] = W[0] * W[2]; U[3] = W[0] * W[3]; U[4] = E;
-  V5<T> Us;
-  Us[0] = fac;
-  Us[1] = fac * Ss;
-  Us[2] = fac * W[2];
-  Us[3] = fac * W[3];
-  const T Er = FastMath<T>::on ? E * (rs * rs) : vdiv(E, W[0]);  // E / rho
-  Us[4] = fac * (Er + (Ss - W[1]) * (Ss + vdiv(W[4], m)));
-  V5<T> Fs;
+  if constexpr (FastMath<T>::on) {
+    // FP32: F* = F + S (U* - U) with one reciprocal r = 1/(S - S*):
+    // U* = m r (1, S*, v, w, E/rho + (S* - u)(S* + p/m)), so with
+    // d = m r - rho the momentum and energy parts are
+    //   rho* - rho = d, (rho u)* - rho u = m r S* - rho u, transverse d v, d w,
+    //   E* - E = d E / rho + (S* - u)(m r S* + p r).
+    const T r = vrcp(S - Ss);
+    const T fac = m * r;
+    const T d = fac - W[0];
+    const T facS = fac * Ss;
+    const T Er = E * (rs * rs);  // E / rho
+    const T dE = d * Er + (Ss - W[1]) * (facS + W[4] * r);
+    V5<T> Fs;
+    Fs[0] = F[0] + S * d;
+    Fs[1] = F[1] + S * (facS - W[0] * W[1]);
+    Fs[2] = F[2] + S * (d * W[2]);
+    Fs[3] = F[3] + S * (d * W[3]);
+    Fs[4] = F[4] + S * dE;
+    return Fs;
+  } else {
+    T fac = vdiv(m, S - Ss);
+    V5<T> U;
+    U[0] = W[0]; U[1] = W[0] * W[1]; U[2] = W[0] * W[2]; U[3] = W[0] * W[3]; U[4] = E;
+    V5<T> Us;
+    Us[0] = fac;
+    Us[1] = fac * Ss;
+    Us[2] = fac * W[2];
+    Us[3] = fac * W[3];
+    Us[4] = fac * (vdiv(E, W[0]) + (Ss - W[1]) * (Ss + vdiv(W[4], m)));
+    V5<T> Fs;
 #pragma unroll
-  for (int n = 0; n < 5; ++n) Fs[n] = F[n] + S * (Us[n] - U[n]);
-  return Fs;
+    for (int n = 0; n < 5; ++n) Fs[n] = F[n] + S * (Us[n] - U[n]);
+    return Fs;
+  }
 }
 
 // Roe flux; on failure of the linearization (non-positive averaged c^2, or
@@ -477,7 +508,7 @@ HY_DEV V5<T> roe(const V5<T>& L, const V5<T>& R, const Phys<T>& ph, int* fails) 
     ++*fails;
     return ph.roe_fb_hllc ? hllc(L, R, ph) : hlle(L, R, ph);
   }
-  V5<T> FL = flux_of(L, ph), FR = flux_of(R, ph);
+  V5<T> FL = flux_with_energy(L, EL), FR = flux_with_energy(R, ER);
   T l1 = vabs(a.u - ct) * a1, l2 = vabs(a.u), l5 = vabs(a.u + ct) * a5;
   T l2a2 = l2 * a2, l2a3 = l2 * a3, l2a4 = l2 * a4;
   V5<T> F;
