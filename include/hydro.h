@@ -253,6 +253,9 @@ int hydro_accumulate(void* acc, const void* x, double w, long long n, int flags,
  *             count = ngx*ngy*ngz, group index (gz*ngy + gy)*ngx + gx; the
  *             ghost cells are read from the neighbouring groups (the
  *             preparation step fused into the solver).  Fused path only.
+ *             A z-slab of groups (ngx*ngy groups) must hold less than 4 GiB
+ *             (FP32: at most 52,428 groups, FP64: 26,214); a segment beyond
+ *             that gets NaN outputs.
  * out is [count][5][16][16][16], flux as for hydro_solve_groups or NULL. */
 struct hydro_seg {
   const void* in;
@@ -273,7 +276,8 @@ struct hydro_seg {
  * with dt read from the device double *dt_dev (times dt_scale).  The ghost
  * cells are read from the neighbouring groups of box_in, so no ghosted copy
  * is made (the preparation step of Sec. 4.2 fused into the solver).  nx,
- * ny, nz positive multiples of 16; box_out must not overlap box_in.
+ * ny, nz positive multiples of 16 with a z-slab of (nx/16)(ny/16) groups
+ * below 4 GiB (else HYDRO_EINVAL); box_out must not overlap box_in.
  * flux_out as for hydro_solve_groups, or NULL.  Fused path only
  * (HYDRO_EUNSUPPORTED otherwise).
  */

@@ -427,6 +427,8 @@ int hydro_step_box(const void* box_in, void* box_out, void* flux_out, int nx, in
     return fail(HYDRO_EUNSUPPORTED, "box path not built for this combination");
   const bool f64 = (flags & HYDRO_F64) != 0;
   const size_t esz = f64 ? 8 : 4;
+  if ((long long)(nx / 16) * (ny / 16) * 5 * 4096 * (long long)esz >= (1LL << 32))
+    return fail(HYDRO_EINVAL, "a z-slab of groups ((nx/16)(ny/16) groups) must hold less than 4 GiB");
   const long long G = (long long)(nx / 16) * (ny / 16) * (nz / 16);
   const int nf = (flags & HYDRO_FLUX_MID) ? 3 : 2;
   const size_t bb = (size_t)G * 5 * 4096 * esz, fb = (size_t)G * 3 * nf * 5 * 256 * esz;

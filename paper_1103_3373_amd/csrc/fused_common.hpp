@@ -131,68 +131,129 @@ template <typename T> HY_DEV Phys<T> make_phys(const FusedArgs<T>& a) {
   return ph;
 }
 
+// Pointers qualified with the global address space.  A load through a
+// generic pointer is a FLAT access: it counts against the LDS wait counter
+// too, and the compiler must treat its result as possibly per-lane.
+template <typename T> using gptr = __attribute__((address_space(1))) T*;
+
+// Workgroup-uniform values: readfirstlane puts them in scalar registers, so
+// the arithmetic on them is scalar and branches on them do not diverge.
+HY_DEV int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+HY_DEV long long uni(long long v) {
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(unsigned long long)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)((unsigned long long)v >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+HY_DEV double uni(double v) { return __longlong_as_double(uni(__double_as_longlong(v))); }
+template <typename P> HY_DEV P* uni(P* p) { return reinterpret_cast<P*>(uni((long long)(uintptr_t)p)); }
+
+// Global store / load at a uniform base plus a per-lane byte offset (the
+// base + 32-bit offset addressing form of the memory instructions).
+template <typename T> HY_DEV void gstore(T* base, unsigned byte_off, T v) {
+  *(gptr<T>)((gptr<char>)(gptr<T>)base + byte_off) = v;
+}
+template <typename T> HY_DEV T gload(const T* base, unsigned byte_off) {
+  return *(gptr<const T>)((gptr<const char>)(gptr<const T>)base + byte_off);
+}
+
+// The segment a work item belongs to, as workgroup-uniform values.
+struct USeg {
+  const void* in;
+  void* out;
+  void* flux;
+  double dh;
+  long long first;
+  int ngx, ngy, ngz;
+  int box;
+};
+
 // Segment of global group grp (segments sorted by first group; `seg` is a
 // cursor that only moves forward in a persistent loop) and its time step.
 template <typename T>
-HY_DEV const Seg* find_seg(const FusedArgs<T>& a, long long grp, int& seg, double& dt) {
-  const Seg* S;
+HY_DEV USeg find_seg(const FusedArgs<T>& a, long long grp, int& seg, double& dt) {
+  USeg u;
   if (a.segs) {
-    while (seg + 1 < a.n_segs && a.segs[seg + 1].first <= grp) ++seg;
-    while (seg > 0 && a.segs[seg].first > grp) --seg;
-    S = &a.segs[seg];
-    dt = *S->dt * S->dt_scale;
+    const gptr<const Seg> segs = (gptr<const Seg>)a.segs;
+    while (seg + 1 < a.n_segs && segs[seg + 1].first <= grp) ++seg;
+    while (seg > 0 && segs[seg].first > grp) --seg;
+    seg = uni(seg);
+    const gptr<const Seg> S = segs + seg;
+    u = USeg{S->in, S->out, S->flux, S->dh, S->first, S->ngx, S->ngy, S->ngz, S->box};
+    dt = *(gptr<const double>)S->dt * S->dt_scale;
   } else {
-    S = &a.seg0;
-    dt = S->dt ? *S->dt * S->dt_scale : a.dt0;
+    const Seg& S = a.seg0;
+    u = USeg{S.in, S.out, S.flux, S.dh, S.first, S.ngx, S.ngy, S.ngz, S.box};
+    dt = S.dt ? *(gptr<const double>)S.dt * S.dt_scale : a.dt0;
   }
-  return S;
+  u.in = uni(u.in);
+  u.out = uni(u.out);
+  u.flux = uni(u.flux);
+  u.dh = uni(u.dh);
+  u.first = uni(u.first);
+  u.ngx = uni(u.ngx);
+  u.ngy = uni(u.ngy);
+  u.ngz = uni(u.ngz);
+  u.box = uni(u.box);
+  dt = uni(dt);
+  return u;
+}
+
+// Box segments address a cell by a 32-bit byte offset within a z-slab of
+// groups (ngx * ngy groups), so a slab must hold less than 4 GiB; a segment
+// beyond that gets NaN outputs.
+template <typename T> HY_DEV bool slab_fits(const USeg& S) {
+  return !S.box || (unsigned long long)S.ngx * (unsigned long long)S.ngy * (5ull * 4096ull * sizeof(T)) < (1ull << 32);
 }
 
 // Reader of the conserved cells of one column (x, y fixed, interior-relative)
 // of one group: a ghosted group array of width G (N = 16 + 2G), or, in box
-// mode, the periodic box stored as groups.  The (x, y) part of the address
-// is formed once per group; a load only adds the z part.
+// mode, the periodic box stored as groups.  The address of a cell is a
+// uniform base (the group or box, the z plane and the variable) plus the
+// column's byte offset, formed once per group; box mode keeps that offset
+// below 4 GiB (the host rejects boxes whose z-slab of groups is larger).
 template <typename T, int G> struct ColumnReader {
   static constexpr int N = 16 + 2 * G;
   static constexpr long NC = (long)N * N * N;
-  const T* col;     // address of the column's cell at z = 0 (box: of the z-group 0 slab)
-  bool box;
-  int bz0, bnz;     // box mode: first z of the group, box size in z
-  long zgs;         // box mode: elements between z-neighbouring groups
-  HY_DEV void init(const Seg* S, long long lg, int x, int y) {
-    box = S->box != 0;
+  const char* base;  // uniform: box mode the box, else the group's array
+  unsigned off;      // this column's byte offset from `base` (box: in z-group 0)
+  int box;           // uniform
+  int bz0, bnz;      // box mode, uniform: first z of the group, box size in z
+  long zgs;          // box mode, uniform: elements between z-neighbouring groups
+  HY_DEV void init(const USeg& S, long long lg, int x, int y) {
+    box = S.box;
     if (box) {
-      const int ngx = S->ngx, ngy = S->ngy;
+      const int ngx = S.ngx, ngy = S.ngy, l = (int)lg;
       const int bnx = ngx * 16, bny = ngy * 16;
-      bnz = S->ngz * 16;
-      const int bx0 = (int)(lg % ngx) * 16, by0 = (int)((lg / ngx) % ngy) * 16;
-      bz0 = (int)(lg / ((long long)ngx * ngy)) * 16;
+      bnz = S.ngz * 16;
+      const int bx0 = (l % ngx) * 16, by0 = ((l / ngx) % ngy) * 16;
+      bz0 = (l / (ngx * ngy)) * 16;
       int cx = bx0 + x, cy = by0 + y;
       cx += cx < 0 ? bnx : 0; cx -= cx >= bnx ? bnx : 0;
       cy += cy < 0 ? bny : 0; cy -= cy >= bny ? bny : 0;
       zgs = (long)ngx * ngy * 5 * 4096;
-      col = reinterpret_cast<const T*>(S->in) + ((long)(cy >> 4) * ngx + (cx >> 4)) * 5 * 4096 +
-            ((cy & 15) * 16 + (cx & 15));
+      base = reinterpret_cast<const char*>(S.in);
+      off = (unsigned)(((cy >> 4) * ngx + (cx >> 4)) * 5 * 4096 + ((cy & 15) * 16 + (cx & 15))) * (unsigned)sizeof(T);
     } else {
-      col = reinterpret_cast<const T*>(S->in) + lg * 5 * NC + (long)(y + G) * N + (x + G) + (long)G * N * N;
+      base = reinterpret_cast<const char*>(reinterpret_cast<const T*>(S.in) + lg * 5 * NC);
+      off = (unsigned)(((y + G) * N + (x + G) + G * N * N) * (int)sizeof(T));
       bz0 = bnz = 0;
       zgs = 0;
     }
   }
   HY_DEV V5<T> load(int z) const {
     V5<T> u;
+    long zo;
     if (box) {
       int cz = bz0 + z;
       cz += cz < 0 ? bnz : 0;
       cz -= cz >= bnz ? bnz : 0;
-      const T* p = col + (cz >> 4) * zgs + (cz & 15) * 256;
-#pragma unroll
-      for (int n = 0; n < 5; ++n) u[n] = p[n * 4096];
+      zo = (cz >> 4) * zgs + (cz & 15) * 256;
     } else {
-      const T* p = col + (long)z * N * N;
-#pragma unroll
-      for (int n = 0; n < 5; ++n) u[n] = p[n * NC];
+      zo = (long)z * N * N;
     }
+    const long vs = box ? 4096 : NC;
+#pragma unroll
+    for (int n = 0; n < 5; ++n) u[n] = gload(reinterpret_cast<const T*>(base) + zo + n * vs, off);
     return u;
   }
 };

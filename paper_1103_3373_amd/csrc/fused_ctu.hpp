@@ -61,11 +61,11 @@ constexpr int oDH = oF1 + 10 * kF1;  // [5][kSQ] lab order, (y+1) 18 + (x+1)
 constexpr int kLds = oDH + 5 * kSQ;
 constexpr int oF2 = oS;              // [2][5][kF2] frame of d, b 17 + (a+1): slopes are dead by then
 static_assert(10 * kF2 <= 10 * kS, "final fluxes alias the slopes");
-// After the T-typed area: addresses of the ring-corner and outer columns of
+// After the T-typed area: byte offsets of the ring-corner and outer columns of
 // the current group (column ids 320 .. 467), formed once per group, then the
 // workgroup's two diagnostic counters (Roe fallbacks, floor hits).
 constexpr int kOuterCols = 148;
-constexpr size_t kLdsBytes(size_t elem) { return kLds * elem + kOuterCols * sizeof(void*) + 2 * sizeof(unsigned); }
+constexpr size_t kLdsBytes(size_t elem) { return kLds * elem + kOuterCols * sizeof(unsigned) + 2 * sizeof(unsigned); }
 
 // Diagnostic counts go straight to LDS counters (rare events), so no
 // register carries them through the plane loop.
@@ -119,8 +119,8 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
   T* sF1 = sm + oF1;
   T* sDH = sm + oDH;
   T* sF2 = sm + oF2;
-  const T** sOC = reinterpret_cast<const T**>(smem_raw + kLds * sizeof(T));
-  const Tally tally{reinterpret_cast<unsigned*>(smem_raw + kLds * sizeof(T) + kOuterCols * sizeof(void*))};
+  unsigned* sOC = reinterpret_cast<unsigned*>(smem_raw + kLds * sizeof(T));
+  const Tally tally{reinterpret_cast<unsigned*>(smem_raw + kLds * sizeof(T) + kOuterCols * sizeof(unsigned))};
 
   const int tid = threadIdx.x;
   const Column<int> col = column_of<G>(tid);
@@ -153,19 +153,22 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
   const GroupOrder order = group_order(a.n_groups / ZR);
   for (long long item = order.first; item < order.end; item += order.stride) {
     double dt;
-    const Seg* S = find_seg(a, item * ZR, seg, dt);
-    long long lg = item * ZR - S->first;  // the item's first group (local)
+    const USeg S = find_seg(a, item * ZR, seg, dt);
+    long long lg = item * ZR - S.first;  // the item's first group (local)
     int gzs = 0;                           // groups between z neighbours
     if constexpr (ZR > 1) {
       // item -> (column c, run r) of the box; group (r ZR + j) nxy + c
-      const int nxy = S->ngx * S->ngy, li = (int)(item - S->first / ZR);
+      const int nxy = S.ngx * S.ngy, li = (int)(item - S.first / ZR);
       lg = (long long)(li / nxy) * ZR * nxy + li % nxy;
       gzs = nxy;
     }
-    T* __restrict__ O = reinterpret_cast<T*>(S->out) + lg * 5 * 4096;
-    T* __restrict__ FO = (ZR == 1 && S->flux) ? reinterpret_cast<T*>(S->flux) + lg * 3 * a.nf * 5 * 256 : nullptr;
-    ph.dtdh = (T)(dt / S->dh);
-    ph.hdtdh = (T)(0.5 * dt / S->dh);
+    T* __restrict__ O = reinterpret_cast<T*>(S.out) + lg * 5 * 4096;
+    T* __restrict__ FO = (ZR == 1 && S.flux) ? reinterpret_cast<T*>(S.flux) + lg * 3 * a.nf * 5 * 256 : nullptr;
+    // A box segment beyond the addressing limit gets NaN outputs: a NaN dt/dh
+    // makes every updated cell NaN, and the face fluxes get NaN added.
+    const T poison = slab_fits<T>(S) ? T(0) : T(__builtin_nan(""));
+    ph.dtdh = (T)(dt / S.dh) + poison;
+    ph.hdtdh = (T)(0.5 * dt / S.dh) + poison;
     // The group's cells (ghosts included) come from the ghosted input or, in
     // box mode, straight from the periodic grouped box.
     ColumnReader<T, G> rd;
@@ -176,7 +179,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
         const Column<int> oc = column_of<G>(c);
         ColumnReader<T, G> orr;
         orr.init(S, lg, oc.x, oc.y);
-        sOC[c - 320] = orr.col;
+        sOC[c - 320] = orr.off;
       }
     }
     auto load_cons = [&](int z) -> V5<T> { return rd.load(z); };
@@ -252,7 +255,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
         for (int c = tid; c < nCols; c += NT - 320) {
           const Column<int> oc = column_of<G>(c);
           ColumnReader<T, G> orr = rd;  // z part of the group
-          orr.col = sOC[c - 320];
+          orr.off = sOC[c - 320];
           const V5<T> wl = prim_of(orr.load(t), ph);
           sts5(sP, kP, (oc.y + G) * N + (oc.x + G), wl);
           sts5(sQ, kP, (oc.x + G) * N + (oc.y + G), to_frame<1>(wl));
@@ -392,7 +395,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
           if constexpr (ZR > 1) Og += (long)((t - 1) >> 4) * gzs * (5 * 4096);
           const int o = (((t - 1) & 15) * 16 + y) * 16 + x;
 #pragma unroll
-          for (int n = 0; n < 5; ++n) Og[n * 4096 + o] = u[n] - ph.dtdh * (acc[n] + hn[n]);
+          for (int n = 0; n < 5; ++n) gstore(Og + n * 4096, (unsigned)o * (unsigned)sizeof(T), u[n] - ph.dtdh * (acc[n] + hn[n]));
         }
         if (t >= 0 && t < nzt) {
           V5<T> fx = sub5(lds5(sF2, kF2, y * 17 + x + 1), lds5(sF2, kF2, y * 17 + x));
@@ -404,7 +407,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
           const int f = (t == 0) ? 0 : (t == 16 ? 1 : (t == 8 && a.nf == 3 ? 2 : -1));
           if (f >= 0) {
 #pragma unroll
-            for (int n = 0; n < 5; ++n) FO[((2 * a.nf + f) * 5 + n) * 256 + y * 16 + x] = hn[n];
+            for (int n = 0; n < 5; ++n) gstore(FO + ((2 * a.nf + f) * 5 + n) * 256, (unsigned)(y * 16 + x) * (unsigned)sizeof(T), hn[n] + poison);
           }
         }
       } else if (FO && t >= 0 && t < nzt) {
@@ -415,7 +418,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
           const int fi = f == 0 ? -1 : (f == 1 ? 15 : 7);  // face index of offsets 0, 16, 8
           const V5<T> v = from_frame_d(lds5(sF2 + (d ? 5 * kF2 : 0), kF2, s * 17 + fi + 1), d);
 #pragma unroll
-          for (int n = 0; n < 5; ++n) FO[(((d ? 1 : 0) * a.nf + f) * 5 + n) * 256 + t * 16 + s] = v[n];
+          for (int n = 0; n < 5; ++n) gstore(FO + (((d ? 1 : 0) * a.nf + f) * 5 + n) * 256, (unsigned)(t * 16 + s) * (unsigned)sizeof(T), v[n] + poison);
         }
       }
       if (col.cross) {

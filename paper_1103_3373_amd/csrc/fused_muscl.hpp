@@ -84,15 +84,16 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
   const GroupOrder order = group_order(a.n_groups);
   for (long long grp = order.first; grp < order.end; grp += order.stride) {
     double dt;
-    const Seg* S = find_seg(a, grp, seg, dt);
-    const long long lg = grp - S->first;
-    T* __restrict__ O = reinterpret_cast<T*>(S->out) + lg * 5 * 4096;
-    T* __restrict__ FO = S->flux ? reinterpret_cast<T*>(S->flux) + lg * 3 * a.nf * 5 * 256 : nullptr;
-    ph.dtdh = (T)(dt / S->dh);
-    ph.hdtdh = (T)(0.5 * dt / S->dh);
-    // A segment that is no box in a launch that declared boxes only: its
-    // half step was not computed for it, so its output is made NaN.
-    const T poison = (MODE == 1 && a.wstar_box && !S->box) ? __builtin_nan("") : T(0);
+    const USeg S = find_seg(a, grp, seg, dt);
+    const long long lg = grp - S.first;
+    T* __restrict__ O = reinterpret_cast<T*>(S.out) + lg * 5 * 4096;
+    T* __restrict__ FO = S.flux ? reinterpret_cast<T*>(S.flux) + lg * 3 * a.nf * 5 * 256 : nullptr;
+    ph.dtdh = (T)(dt / S.dh);
+    ph.hdtdh = (T)(0.5 * dt / S.dh);
+    // A segment that is no box in a launch that declared boxes only (its
+    // half step was not computed for it), or a box whose z-slab of groups
+    // exceeds 4 GiB: its output is made NaN.
+    const T poison = ((MODE == 1 && a.wstar_box && !S.box) || !slab_fits<T>(S)) ? T(__builtin_nan("")) : T(0);
 
     // Sources: MHM reads U^n (ghost width G) and converts; VL reads the
     // half-step primitive W* from the predictor's scratch (ghost width G)
@@ -105,13 +106,13 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
       if (a.wstar_box) {
         // W* of this segment is a grouped periodic box of the segment's
         // shape: ghost cells come from the neighbouring groups.
-        Seg w = *S;
-        w.in = a.wstar + S->first * 5 * 4096;
-        src.init(&w, lg, col.x, col.y);
+        USeg w = S;
+        w.in = a.wstar + S.first * 5 * 4096;
+        src.init(w, lg, col.x, col.y);
       } else {
-        Seg w{};
+        USeg w{};
         w.in = a.wstar;
-        src.init(&w, grp, col.x, col.y);
+        src.init(w, grp, col.x, col.y);
       }
       upd.init(S, lg, col.x, col.y);
     }
@@ -299,7 +300,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
           V5<T> u = ucons(t - 1);
           const int o = ((t - 1) * 16 + y) * 16 + x;
 #pragma unroll
-          for (int n = 0; n < 5; ++n) O[n * 4096 + o] = u[n] - ph.dtdh * (acc[n] + hn[n]) + poison;
+          for (int n = 0; n < 5; ++n) gstore(O + n * 4096, (unsigned)o * (unsigned)sizeof(T), u[n] - ph.dtdh * (acc[n] + hn[n]) + poison);
         }
         if (t >= 0 && t <= 15) {
           V5<T> fx = sub5(lds5(sF2, kF2, y * 17 + x + 1), lds5(sF2, kF2, y * 17 + x));
@@ -311,7 +312,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
           const int f = (t == 0) ? 0 : (t == 16 ? 1 : (t == 8 && a.nf == 3 ? 2 : -1));
           if (f >= 0) {
 #pragma unroll
-            for (int n = 0; n < 5; ++n) FO[((2 * a.nf + f) * 5 + n) * 256 + y * 16 + x] = hn[n];
+            for (int n = 0; n < 5; ++n) gstore(FO + ((2 * a.nf + f) * 5 + n) * 256, (unsigned)(y * 16 + x) * (unsigned)sizeof(T), hn[n] + poison);
           }
         }
       } else if (FO && t >= 0 && t <= 15) {
@@ -322,7 +323,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
           const int fi = f == 0 ? -1 : (f == 1 ? 15 : 7);
           const V5<T> v = from_frame_d(lds5(sF2 + (d ? 5 * kF2 : 0), kF2, s * 17 + fi + 1), d);
 #pragma unroll
-          for (int n = 0; n < 5; ++n) FO[(((d ? 1 : 0) * a.nf + f) * 5 + n) * 256 + t * 16 + s] = v[n];
+          for (int n = 0; n < 5; ++n) gstore(FO + (((d ? 1 : 0) * a.nf + f) * 5 + n) * 256, (unsigned)(t * 16 + s) * (unsigned)sizeof(T), v[n] + poison);
         }
       }
     }

@@ -63,6 +63,8 @@ __global__ void __launch_bounds__(threads<G>(), 2) vl_predict_kernel(FusedArgs<T
     out_col = active && x >= -Gs && x <= 15 + Gs && y >= -Gs && y <= 15 + Gs;
   }
   const int pc = (y + G) * N + (x + G);  // the column's cell in the plane
+  // byte offset of the column's cell in a half-step plane (output columns)
+  const unsigned wo = out_col ? (unsigned)(((y + Gs) * Ns + (x + Gs)) * (int)sizeof(T)) : 0u;
   int fails = 0, floors = 0;
   Phys<T> ph = make_phys(a);
 
@@ -70,13 +72,16 @@ __global__ void __launch_bounds__(threads<G>(), 2) vl_predict_kernel(FusedArgs<T
   const GroupOrder order = group_order(a.n_groups);
   for (long long grp = order.first; grp < order.end; grp += order.stride) {
     double dt;
-    const Seg* S = find_seg(a, grp, seg, dt);
-    const long long lg = grp - S->first;
-    ph.dtdh = (T)(dt / S->dh);
-    ph.hdtdh = (T)(0.5 * dt / S->dh);
+    const USeg S = find_seg(a, grp, seg, dt);
+    const long long lg = grp - S.first;
+    // A box segment beyond the addressing limit: a NaN dt/dh makes every
+    // half-step state NaN.
+    const T poison = slab_fits<T>(S) ? T(0) : T(__builtin_nan(""));
+    ph.dtdh = (T)(dt / S.dh) + poison;
+    ph.hdtdh = (T)(0.5 * dt / S.dh) + poison;
     ColumnReader<T, G> rd;
     rd.init(S, lg, active ? x : 0, active ? y : 0);
-    T* __restrict__ Wo = a.wstar + grp * 5 * NCs + ((long)(y + Gs) * Ns + (x + Gs));
+    T* __restrict__ Wo = a.wstar + grp * 5 * NCs;  // the group's half-step array (uniform)
 
     V5<T> u0, w0, u1, w1, hm, unext;
     if (active) {
@@ -131,7 +136,7 @@ __global__ void __launch_bounds__(threads<G>(), 2) vl_predict_kernel(FusedArgs<T
         floors += floor_state(w, ph);
         T* o = Wo + (long)(z + Gs) * Ns * Ns;
 #pragma unroll
-        for (int n = 0; n < 5; ++n) o[n * NCs] = w[n];
+        for (int n = 0; n < 5; ++n) gstore(o + n * NCs, wo, w[n]);
         hm = hp;
       }
       if (active) {

@@ -73,6 +73,13 @@ def test_argument_validation(L):
                                            1.4, 2, 1, rs, 1, fl, None)
     assert step(3, 0) == EUNSUP
     assert step(0, 0x80) == EUNSUP
+    # Box cells are addressed by 32-bit byte offsets within a z-slab of
+    # groups: a slab of 4 GiB or more is rejected before any device call.
+    big = lambda nx, ny, fl: L.hydro_step_box(P(0x1000), P(0x100000000000), None, nx, ny, 16, P(0x2000), 1.0,
+                                              1.0 / 32, 1.4, 2, 1, 1, 1, fl, None)
+    assert big(16 * 229, 16 * 229, 0) == EINVAL        # 52,441 groups x 80 KiB
+    assert b"4 GiB" in L.hydro_last_error()
+    assert big(16 * 162, 16 * 162, 0x01) == EINVAL     # FP64: 26,244 groups x 160 KiB
     assert _solve(L, limiter=4) == EINVAL
     assert _solve(L, flags=0x100) == EINVAL
     assert _solve(L, inp=0, out=0x2000) == EINVAL
