@@ -23,8 +23,8 @@
 //    they share one code path and a wavefront that holds both does not
 //    diverge.
 //  * Per plane: A columns (prims, z trace, H1, dH1) | B x/y slopes |
-//    (PPM) C1 x/y edges, once per face | C x/y monotonization and traces |
-//    D x/y Riemann set 1 | E corrected x/y Riemann set 2 and z correction
+//    C x/y face values (PPM: both edges of the cell), monotonization and
+//    traces | D x/y Riemann set 1 | E corrected x/y Riemann set 2 and z correction
 //    + z Riemann set 2 | F conservative update and flux store.  The update
 //    of plane t-1 completes in plane t once its upper z flux exists.
 //  * The correction of a face state is done by the task that solves that
@@ -127,7 +127,11 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
   const int pcol = (col.y + G) * N + (col.x + G);  // primitive plane index, lab
   const int qcol = (col.x + G) * N + (col.y + G);  // the same cell in the transposed plane
   const int sqc = (col.y + 1) * 18 + (col.x + 1);  // 18x18 square index (cross columns)
-  const bool interior = tid < 256;
+  // Column classes are whole wavefronts (interior: waves 0-3, cross: 0-4),
+  // so the tests are made on a wave-uniform value and do not diverge.
+  const int wtid = uni(tid & ~63);
+  const bool interior = wtid < 256;
+  const bool cross = wtid < 320;
   constexpr int nCols = 324 + 4 * (G - 1) * 18;  // columns that feed the primitive plane
   static_assert(nCols - 320 <= kOuterCols, "outer column table");
   if (tid < 2) tally.c[tid] = 0u;
@@ -140,10 +144,9 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
   }
 
   // Task counts per direction.  Slopes: PPM needs a in -2..17 (edges of the
-  // traced cells), PLM a in -1..16.  PPM edges: faces a+1/2, a in -2..16.
+  // traced cells), PLM a in -1..16.
   constexpr int wS = PPM ? 20 : 18, a0S = PPM ? -2 : -1;
   constexpr int nS = wS * 18;
-  constexpr int nE = 19 * 18;
 
   // Work items: single groups, or runs of ZR z-consecutive groups of one
   // periodic box (flux output off), marched through in one pass: the z
@@ -173,7 +176,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
     // box mode, straight from the periodic grouped box.
     ColumnReader<T, G> rd;
     rd.init(S, lg, col.x, col.y);
-    if (!col.cross) {
+    if (!cross) {
       // Each thread reads back only the slots it writes: no barrier needed.
       for (int c = tid; c < nCols; c += NT - 320) {
         const Column<int> oc = column_of<G>(c);
@@ -194,7 +197,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
     V5<T> acc;          // flux differences of the plane being updated, all but its upper z face (lab)
 
     // ---- prologue: window and traced states of plane -1 -------------------
-    if (col.cross) {
+    if (cross) {
       if (PPM) {
         V5<T> wa = zprim(-3), wb = zprim(-2);
         w0 = zprim(-1);
@@ -221,34 +224,40 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
     for (int t = -1; t <= nzt; ++t) {
       // ---- A: columns: primitive plane t; trace plane t+1; H1(t+1/2) -------
       V5<T> nzm, nzp;  // traced states of plane t+1
-      if (col.cross) {
+      if (cross) {
         const V5<T> wl = from_frame<2>(w0);
         sts5(sP, kP, pcol, wl);
         sts5(sQ, kP, qcol, to_frame<1>(wl));
-        if (t < nzt) {
-          if (PPM) {
-            V5<T> w3 = zprim(t + 3);
-            V5<T> s2 = slope(w1, w2, w3, ph);
-            V5<T> e1 = ppm_edge(w1, w2, s1, s2);
-            nzm = e0;
-            nzp = e1;
-            ppm_mono(w1, nzm, nzp);
-            ctu_trace<true>(w1, nzm, nzp, ph);
-            w0 = w1; w1 = w2; w2 = w3; s1 = s2; e0 = e1;
-          } else {
-            V5<T> w3 = zprim(t + 2);
-            V5<T> sb = slope(w0, w1, w3, ph);
-            plm_faces(w0, w1, w3, sb, ph, nzm, nzp);
-            ctu_trace<false>(w1, nzm, nzp, ph);
-            w0 = w1; w1 = w3;
-          }
-          tally.floors(floor_state(nzm, ph) + floor_state(nzp, ph));
-          int nf = 0;
-          V5<T> h1p = riemann<RS>(ztp, nzm, ph, &nf);  // H1(t+1/2)
-          tally.fails(nf);
-          if (t >= 0) sts5(sDH, kSQ, sqc, from_frame<2>(sub5(h1p, h1m)));
-          h1m = h1p;
+        // The last plane (t == nzt) needs nothing above it.  The work is done
+        // anyway, on a clamped plane index, so that the column's register
+        // window advances the same way on every iteration (no copies at a
+        // join); its diagnostics are not counted and its results are unused.
+        const bool live = t < nzt;
+        if (PPM) {
+          V5<T> w3 = zprim(live ? t + 3 : t + 2);
+          V5<T> s2 = slope(w1, w2, w3, ph);
+          V5<T> e1 = ppm_edge(w1, w2, s1, s2);
+          nzm = e0;
+          nzp = e1;
+          ppm_mono(w1, nzm, nzp);
+          ctu_trace<true>(w1, nzm, nzp, ph);
+          w0 = w1; w1 = w2; w2 = w3; s1 = s2; e0 = e1;
+        } else {
+          V5<T> w3 = zprim(live ? t + 2 : t + 1);
+          V5<T> sb = slope(w0, w1, w3, ph);
+          plm_faces(w0, w1, w3, sb, ph, nzm, nzp);
+          ctu_trace<false>(w1, nzm, nzp, ph);
+          w0 = w1; w1 = w3;
         }
+        const int fl = floor_state(nzm, ph) + floor_state(nzp, ph);
+        int nf = 0;
+        V5<T> h1p = riemann<RS>(ztp, nzm, ph, &nf);  // H1(t+1/2)
+        if (live) {
+          tally.floors(fl);
+          tally.fails(nf);
+        }
+        if (t >= 0) sts5(sDH, kSQ, sqc, from_frame<2>(sub5(h1p, h1m)));
+        h1m = h1p;
       } else {
         // Ring corners and outer columns (column ids 320 .. nCols-1), strided
         // over the threads that own no cross column.
@@ -275,25 +284,6 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
       }
       __syncthreads();
 
-      // ---- C1 (PPM): x and y edge values, once per face --------------------
-      if (PPM) {
-        for (int q = tid; q < 2 * nE; q += NT) {
-          const bool d = q >= nE;
-          const int r = d ? q - nE : q;
-          const int aa = r % 19 - 2, b = r / 19 - 1;  // face between cells aa and aa+1
-          const T* pl = d ? sQ : sP;
-          const T* ss = sS + (d ? 5 * kS : 0);
-          const int c = (b + G) * N + (aa + G);
-          const int si = (b + 1) * 20 + (aa + 2);
-          V5<T> e = ppm_edge(lds5(pl, kP, c), lds5(pl, kP, c + 1), lds5(ss, kS, si), lds5(ss, kS, si + 1));
-          T* w = sW + (d ? 10 * kSQ : 0);
-          const int wi = (b + 1) * 18 + (aa + 1);  // cell aa
-          if (aa >= -1) sts5(w + 5 * kSQ, kSQ, wi, e);  // right face of cell aa
-          if (aa <= 15) sts5(w, kSQ, wi + 1, e);        // left face of cell aa+1
-        }
-        __syncthreads();
-      }
-
       // ---- C: traced x and y face states of plane t (frame of d) -----------
       for (int q = tid; q < 2 * kSQ; q += NT) {
         const bool d = q >= kSQ;
@@ -305,8 +295,15 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
         const V5<T> wc = lds5(pl, kP, c);
         V5<T> fl, fr;
         if (PPM) {
-          fl = lds5(w, kSQ, r);
-          fr = lds5(w + 5 * kSQ, kSQ, r);
+          // Both PPM edges of the cell.  An edge shared by two cells is
+          // evaluated by each of them, with the same operands in the same
+          // order, so both get the same value; that costs less than a phase
+          // of its own (index math, a barrier, a partly filled wavefront).
+          const T* ss = sS + (d ? 5 * kS : 0);
+          const int si = (b + 1) * 20 + (aa + 2);
+          const V5<T> s0 = lds5(ss, kS, si);
+          fl = ppm_edge(lds5(pl, kP, c - 1), wc, lds5(ss, kS, si - 1), s0);
+          fr = ppm_edge(wc, lds5(pl, kP, c + 1), s0, lds5(ss, kS, si + 1));
           ppm_mono(wc, fl, fr);
         } else {
           const T* ss = sS + (d ? 5 * kS : 0);
@@ -421,7 +418,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
           for (int n = 0; n < 5; ++n) gstore(FO + (((d ? 1 : 0) * a.nf + f) * 5 + n) * 256, (unsigned)(t * 16 + s) * (unsigned)sizeof(T), v[n] + poison);
         }
       }
-      if (col.cross) {
+      if (cross) {
         ztm = nzm;
         ztp = nzp;
       }

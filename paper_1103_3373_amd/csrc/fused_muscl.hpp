@@ -13,8 +13,8 @@
 //   full dt.
 //
 // Per plane t (t = -1 .. 16): A columns (primitive plane t, z face states of
-// plane t) | B x/y slopes | (PPM) C1 x/y edges, once per face | C x/y face
-// states | D (MHM) Hancock half step of the cross cells by their column
+// plane t) | B x/y slopes | C x/y face states (PPM: both edges of the cell
+// and monotonization) | D (MHM) Hancock half step of the cross cells by their column
 // threads | E x/y Riemann faces of plane t and the z Riemann face below it |
 // F update of plane t-1 and boundary fluxes.  As in the CTU kernel, every
 // per-direction LDS array is laid out in the direction's own (along,
@@ -67,7 +67,11 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
   const int qcol = (col.x + G) * N + (col.y + G);
   const int sqx = (col.y + 1) * 18 + (col.x + 1);  // the cross cell in the x arrays
   const int sqy = (col.x + 1) * 18 + (col.y + 1);  // ... and in the (transposed) y arrays
-  const bool interior = tid < 256;
+  // Column classes are whole wavefronts (interior: waves 0-3, cross: 0-4),
+  // so the tests are made on a wave-uniform value and do not diverge.
+  const int wtid = uni(tid & ~63);
+  const bool interior = wtid < 256;
+  const bool cross = wtid < 320;
   if (tid < 2) tally.c[tid] = 0u;
   __syncthreads();
   Phys<T> ph = make_phys(a);
@@ -78,7 +82,6 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
 
   constexpr int wS = PPM ? 20 : 18, a0S = PPM ? -2 : -1;
   constexpr int nS = wS * 18;
-  constexpr int nE = 19 * 18;
 
   int seg = 0;
   const GroupOrder order = group_order(a.n_groups);
@@ -136,7 +139,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
     V5<T> acc;        // flux differences of the plane being updated, all but its upper z face (lab)
     V5<T> wnext;      // the column's newest z plane, loaded one plane ahead (prims)
     constexpr int zAhead = PPM ? 2 : 1;
-    if (col.cross) {
+    if (cross) {
       if (PPM) {
         V5<T> w3 = zprim(-3), w2 = zprim(-2);
         wa = zprim(-1);
@@ -153,11 +156,11 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
 
     for (int t = -1; t <= 16; ++t) {
       // ---- A: primitive planes t; z face states of plane t -----------------
-      if (col.cross) {
+      if (cross) {
         if (PPM) {
           put_plane(pcol, qcol, from_frame<2>(wa));
           V5<T> wc = to_frame<2>(MODE == 0 ? prim_of(wnext, ph) : wnext);  // plane t + 2
-          if (t + 1 + zAhead <= 16 + zAhead) wnext = src.load(t + 1 + zAhead);
+          wnext = src.load(t + 1 + zAhead <= 16 + zAhead ? t + 1 + zAhead : 16 + zAhead);
           V5<T> sn = slope(wa, wb, wc, ph);
           V5<T> ep = ppm_edge(wa, wb, st, sn);
           zfm = em;
@@ -167,7 +170,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
         } else {
           put_plane(pcol, qcol, from_frame<2>(wb));
           V5<T> wc = to_frame<2>(MODE == 0 ? prim_of(wnext, ph) : wnext);  // plane t + 1
-          if (t + 1 + zAhead <= 16 + zAhead) wnext = src.load(t + 1 + zAhead);
+          wnext = src.load(t + 1 + zAhead <= 16 + zAhead ? t + 1 + zAhead : 16 + zAhead);
           V5<T> s0 = slope(wa, wb, wc, ph);
           plm_faces(wa, wb, wc, s0, ph, zfm, zfp);
           wa = wb; wb = wc;
@@ -190,25 +193,6 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
       }
       __syncthreads();
 
-      // ---- C1 (PPM): x and y edge values, once per face --------------------
-      if (PPM) {
-        for (int q = tid; q < 2 * nE; q += NT) {
-          const bool d = q >= nE;
-          const int r = d ? q - nE : q;
-          const int aa = r % 19 - 2, b = r / 19 - 1;  // face between cells aa and aa+1
-          const T* pl = d ? sQ : sP;
-          const T* ss = sS + (d ? 5 * kS : 0);
-          const int c = (b + G) * N + (aa + G);
-          const int si = (b + 1) * 20 + (aa + 2);
-          V5<T> e = ppm_edge(lds5(pl, kP, c), lds5(pl, kP, c + 1), lds5(ss, kS, si), lds5(ss, kS, si + 1));
-          T* w = sW + (d ? 10 * kSQ : 0);
-          const int wi = (b + 1) * 18 + (aa + 1);
-          if (aa >= -1) sts5(w + 5 * kSQ, kSQ, wi, e);
-          if (aa <= 15) sts5(w, kSQ, wi + 1, e);
-        }
-        __syncthreads();
-      }
-
       // ---- C: x and y face states (frame of d) -----------------------------
       for (int q = tid; q < 2 * kSQ; q += NT) {
         const bool d = q >= kSQ;
@@ -220,8 +204,15 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
         const V5<T> wc = lds5(pl, kP, c);
         V5<T> fl, fr;
         if (PPM) {
-          fl = lds5(w, kSQ, r);
-          fr = lds5(w + 5 * kSQ, kSQ, r);
+          // Both PPM edges of the cell.  An edge shared by two cells is
+          // evaluated by each of them, with the same operands in the same
+          // order, so both get the same value; that costs less than a phase
+          // of its own (index math, a barrier, a partly filled wavefront).
+          const T* ss = sS + (d ? 5 * kS : 0);
+          const int si = (b + 1) * 20 + (aa + 2);
+          const V5<T> s0 = lds5(ss, kS, si);
+          fl = ppm_edge(lds5(pl, kP, c - 1), wc, lds5(ss, kS, si - 1), s0);
+          fr = ppm_edge(wc, lds5(pl, kP, c + 1), s0, lds5(ss, kS, si + 1));
           ppm_mono(wc, fl, fr);
         } else {
           const T* ss = sS + (d ? 5 * kS : 0);
@@ -236,7 +227,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
 
       // ---- D (MHM): Hancock half step of every cross cell ------------------
       if (MODE == 0) {
-        if (col.cross) {
+        if (cross) {
           T* wx = sW;
           T* wy = sW + 10 * kSQ;
           V5<T> xm = lds5(wx, kSQ, sqx), xp = lds5(wx + 5 * kSQ, kSQ, sqx);

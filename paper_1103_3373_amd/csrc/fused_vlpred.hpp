@@ -55,7 +55,7 @@ __global__ void __launch_bounds__(threads<G>(), 2) vl_predict_kernel(FusedArgs<T
       y = side == 2 ? -1 : (side == 3 ? 16 : s);
     }
     active = true;
-    out_col = tid < 256;
+    out_col = uni(tid & ~63) < 256;  // waves 0-3: wave-uniform
   } else {
     active = tid < N * N;
     x = tid % N - G;
@@ -102,7 +102,7 @@ __global__ void __launch_bounds__(threads<G>(), 2) vl_predict_kernel(FusedArgs<T
       if (active) {
         sts5(sP, N * N, pc, w0);
         u1 = unext;
-        if (z + 2 <= 16 + Gs) unext = rd.load(z + 2);
+        unext = rd.load(z + 2 <= 16 + Gs ? z + 2 : 16 + Gs);  // clamped on the last plane
         w1 = prim_of(u1, ph);
         if (out_col) hp = from_frame<2>(riemann<RS>(to_frame<2>(w0), to_frame<2>(w1), ph, &fails));
       }
