@@ -442,6 +442,35 @@ def test_vl_box_segments_in_one_launch(H):
     assert torch.equal(o1, alone[1])
 
 
+def test_box_segment_beyond_slab_limit_is_nan(H):
+    """Box cells are addressed by a 32-bit byte offset within a z-slab of
+    groups.  A batched box segment whose slab holds 4 GiB or more (here FP32,
+    229 x 229 groups = 52,441 x 80 KiB) gets NaN outputs, for CTU and MHM,
+    while a small box segment of the same launch is stepped exactly as alone.
+    (hydro_step_box rejects such a box on the host; see tests/test_abi.py.)"""
+    gamma, ng = 1.4, 229
+    big = torch.zeros((ng * ng, 5, 16, 16, 16), dtype=torch.float32, device="cuda")
+    big[:, 0] = 1.0
+    big[:, 4] = 1.0 / (gamma - 1.0)
+    out_big = torch.empty_like(big)
+    small = _dev(W.box_to_groups(W.lognormal_blast_box(32, gamma=gamma, seed=5, radius_cells=3)), torch.float32)
+    dt_dev = torch.tensor([1e-4], dtype=torch.float64, device="cuda")
+    for scheme in (H.CTU, H.MHM):
+        alone = torch.empty_like(small)
+        H.step_box(small, alone, (32, 32, 32), dt_dev, dh=1 / 32, gamma=gamma, scheme=scheme, recon=H.PPM,
+                   riemann=H.HLLC, char=True)
+        out_small = torch.empty_like(small)
+        rows = [(small, out_small, None, dt_dev, 1.0, 1 / 32, 0, small.shape[0], (2, 2, 2)),
+                (big, out_big, None, dt_dev, 1.0, 1 / 32, small.shape[0], big.shape[0], (ng, ng, 1))]
+        spec = H.make_spec(scheme, H.PPM, H.HLLC, gamma=gamma, char=True)
+        H.solve_batch(H.seg_table(rows, "cuda"), len(rows), small.shape[0] + big.shape[0], spec)
+        torch.cuda.synchronize()
+        assert torch.isnan(out_big).all(), scheme
+        assert torch.equal(out_small, alone), scheme
+    del big, out_big
+    torch.cuda.empty_cache()
+
+
 def test_amr_graph_replay_matches_eager(H):
     """The AMR preparation (group map, padded fill), the flux accumulation and
     the coarse-grid correction captured in a HIP graph: three replays, with
