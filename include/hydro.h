@@ -347,31 +347,32 @@ int hydro_autotune(const struct hydro_spec* spec, int n_groups_hint, void* strea
 /*
  * Pins the launch shape of the fused kernel for `spec`'s specialization in
  * the in-process cache (as if the autotuner had chosen it), for callers that
- * tune offline or need a fixed shape.  grid = persistent workgroup count
- * (0 = default: one or twelve workgroups per compute unit, by variant; a grid
+ * tune offline or need a fixed shape.  grid = persistent workgroup count (0
+ * = default: one or twelve workgroups per compute unit, by variant; a grid
  * larger than a launch's work-item count is clamped to it).  variant =
  * register budget variant: 2 (one workgroup per CU, no register spills) or 4
- * (two workgroups per CU; FP32 only).  zrun = tile depth of a CTU box step
- * without flux output (hydro_step_box): each workgroup marches through zrun
- * z-consecutive patch groups of one column in one pass (a 16 x 16 x 16*zrun
- * tile), so the work items are the box's groups / zrun; 0 = default (the
- * largest of 4, 2 that divides the box's group count in z and leaves two
- * items per resident workgroup slot).  Depths 2 and 4 are built for the
- * FP32 van Leer / characteristic specialization with variant 4 only; the
- * depth used is the largest built one, not above the request, that divides
- * the box's group count in z.  At one tile depth, results do not depend on the
- * grid or variant (bit for bit).  Tile depths differ in the last bits on
- * the first planes of a group that continues a run, whose z slopes and
- * edges come from the kernel's loop body rather than its z prologue (two
- * copies of the same arithmetic the compiler may contract differently).
- * HYDRO_EINVAL for other values (zrun outside 0..64).
+ * (two workgroups per CU; FP32 only).  zrun = tile depth of a box step
+ * without flux output (hydro_step_box; for VL, of its second stage): each
+ * workgroup marches through zrun z-consecutive patch groups of one column in
+ * one pass (a 16 x 16 x 16*zrun tile), so the work items are the box's
+ * groups / zrun; 0 = default (the largest of 4, 2 that divides the box's
+ * group count in z and leaves two items per resident workgroup slot).
+ * Depths 2 and 4 are built for the FP32 van Leer / characteristic
+ * specialization with variant 4 only (CTU with PLM or PPM, MHM and VL with
+ * PPM); the depth used is the largest built one, not above the request, that
+ * divides the box's group count in z.  At one tile depth, results do not
+ * depend on the grid or variant (bit for bit).  Tile depths differ in the
+ * last bits on the first planes of a group that continues a run, whose z
+ * slopes and edges come from the kernel's loop body rather than its z
+ * prologue (two copies of the same arithmetic the compiler may contract
+ * differently). HYDRO_EINVAL for other values (zrun outside 0..64).
  */
 int hydro_set_launch_shape(const struct hydro_spec* spec, int grid, int variant, int zrun);
 
 /*
  * The launch shape hydro_step_box would use for `spec` on an nx x ny x nz
  * box without flux output (host outputs: workgroups, register variant, and
- * groups per z-run, 1 for schemes other than CTU).  No device work.
+ * groups per z-run).  No device work.
  * HYDRO_EINVAL for bad sizes or options.
  */
 int hydro_get_launch_shape(const struct hydro_spec* spec, int nx, int ny, int nz, int* grid, int* variant,

@@ -218,13 +218,13 @@ Tune tuned(int f64, int scheme, int recon, int riemann, int charlim, long long n
   return t;
 }
 
-// Launch shape of a CTU step over one periodic box of ngz groups in z
+// Launch shape of a step over one periodic box of ngz groups in z
 // (n_groups in all) without flux output: the z-run length (the tuned one,
 // or the largest of 4, 2 that divides ngz and still leaves two runs per
 // resident workgroup slot; in any case the largest built length, not above
 // it, that divides ngz) and the grid over the runs.
-Tune tuned_box(int f64, int recon, int riemann, int limiter, int charlim, long long n_groups, int ngz) {
-  Tune t = tuned(f64, HYDRO_CTU, recon, riemann, charlim, n_groups);
+Tune tuned_box(int f64, int scheme, int recon, int riemann, int limiter, int charlim, long long n_groups, int ngz) {
+  Tune t = tuned(f64, scheme, recon, riemann, charlim, n_groups);
   int K = t.zrun;
   if (K <= 0) {
     const long long slots = (long long)cu_count() * (t.waves == 4 ? 2 : 1);
@@ -232,7 +232,7 @@ Tune tuned_box(int f64, int recon, int riemann, int limiter, int charlim, long l
     for (int k : {4, 2})
       if (ngz % k == 0 && n_groups / k >= 2 * slots) { K = k; break; }
   }
-  while (K > 1 && (ngz % K || !hy::ctu_zrun_built(f64, t.waves, limiter, charlim, K))) --K;
+  while (K > 1 && (ngz % K || !hy::zrun_built(scheme, f64, t.waves, recon, limiter, charlim, K))) --K;
   t.zrun = K;
   if (t.grid_box > 0) t.grid = t.grid_box;
   const long long items = n_groups / K;
@@ -442,10 +442,11 @@ int hydro_step_box(const void* box_in, void* box_out, void* flux_out, int nx, in
   hy::Seg seg{box_in, box_out, flux_out, dt_dev, dt_scale, dh, 0, G, nx / 16, ny / 16, nz / 16, 1};
   const int g = ghost_width(scheme, reconstruction);
   // CTU without flux output marches through runs of z-consecutive groups.
-  const Tune tu = (scheme == HYDRO_CTU && !flux_out)
-                      ? tuned_box(f64, reconstruction, riemann, limiter, charlim, G, nz / 16)
-                      : tuned(f64, scheme, reconstruction, riemann, charlim, G);
-  const int zrun = (scheme == HYDRO_CTU && !flux_out) ? tu.zrun : 1;
+  // Without flux output the workgroups march through runs of z-consecutive
+  // groups.
+  const Tune tu = !flux_out ? tuned_box(f64, scheme, reconstruction, riemann, limiter, charlim, G, nz / 16)
+                            : tuned(f64, scheme, reconstruction, riemann, charlim, G);
+  const int zrun = !flux_out ? tu.zrun : 1;
   Workspace& w = ds->ws[st];
   if (int rc = ensure_vl(w, (size_t)G * hy::fused_scratch_per_group(scheme, reconstruction, 1) * esz)) return rc;
   // Passed by value: the kernel reads dt through seg.dt (segs == nullptr and
@@ -763,12 +764,10 @@ int hydro_get_launch_shape(const struct hydro_spec* spec, int nx, int ny, int nz
   const int charlim = (spec->flags & HYDRO_CHAR) ? 1 : 0;
   const long long G = (long long)(nx / 16) * (ny / 16) * (nz / 16);
   std::lock_guard<std::mutex> lock(g_mu);
-  const Tune t = spec->scheme == HYDRO_CTU ? tuned_box(f64, spec->reconstruction, spec->riemann, spec->limiter,
-                                                       charlim, G, nz / 16)
-                                           : tuned(f64, spec->scheme, spec->reconstruction, spec->riemann, charlim, G);
+  const Tune t = tuned_box(f64, spec->scheme, spec->reconstruction, spec->riemann, spec->limiter, charlim, G, nz / 16);
   *grid = t.grid;
   *variant = t.waves;
-  *zrun = spec->scheme == HYDRO_CTU ? t.zrun : 1;
+  *zrun = t.zrun;
   return 0;
 }
 
@@ -862,10 +861,10 @@ int hydro_autotune(const struct hydro_spec* spec, int n_groups_hint, void* strea
       if (grid == n) break;
     }
   }
-  // CTU box steps: tile depth (z-run length) x grid, with the register
-  // variant just chosen, on a synthetic periodic box of the same number of
-  // groups (ngz and ngy the largest powers of two up to 16 that divide it).
-  if (e == hipSuccess && best.grid > 0 && spec->scheme == HYDRO_CTU) {
+  // Box steps: tile depth (z-run length) x grid, with the register variant
+  // just chosen, on a synthetic periodic box of the same number of groups
+  // (ngz and ngy the largest powers of two up to 16 that divide it).
+  if (e == hipSuccess && best.grid > 0) {
     int ngz = 1, ngy = 1;
     while (ngz < 16 && n % (2 * ngz) == 0) ngz *= 2;
     while (ngy < 16 && (n / ngz) % (2 * ngy) == 0) ngy *= 2;
@@ -887,7 +886,7 @@ int hydro_autotune(const struct hydro_spec* spec, int n_groups_hint, void* strea
     float best_box = 1e30f;
     for (int zr : {1, 2, 4}) {
       if (ngz % zr || e != hipSuccess) continue;
-      if (!hy::ctu_zrun_built(f64, best.waves, spec->limiter, charlim, zr)) continue;
+      if (!hy::zrun_built(spec->scheme, f64, best.waves, spec->reconstruction, spec->limiter, charlim, zr)) continue;
       const long long items = n / zr;
       for (int m : mults) {
         long long grid = (long long)cus * m;

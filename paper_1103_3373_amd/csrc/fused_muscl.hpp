@@ -46,8 +46,9 @@ static_assert(10 * kF2 <= 10 * kS, "final fluxes alias the slopes");
 constexpr size_t kLdsBytes(size_t elem) { return kLds * elem + 2 * sizeof(unsigned); }
 
 // FAST as in the CTU kernel: van Leer on characteristic variables fixed at
-// compile time.
-template <typename T, bool PPM, int RS, int WAVES, int MODE, bool FAST>
+// compile time.  ZR as in the CTU kernel: groups per work item (tile depth
+// 16 * ZR), ZR > 1 only for a single periodic box without flux output.
+template <typename T, bool PPM, int RS, int WAVES, int MODE, bool FAST, int ZR>
 __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) {
   constexpr int NT = kThreads;
   constexpr int G = PPM ? 3 : 2;
@@ -83,14 +84,26 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
   constexpr int wS = PPM ? 20 : 18, a0S = PPM ? -2 : -1;
   constexpr int nS = wS * 18;
 
+  // Work items: single groups, or runs of ZR z-consecutive groups of one
+  // periodic box, marched through in one pass (the z prologue and the
+  // planes beyond each end are paid once per run).
+  constexpr int nzt = 16 * ZR;  // interior planes of an item
   int seg = 0;
-  const GroupOrder order = group_order(a.n_groups);
-  for (long long grp = order.first; grp < order.end; grp += order.stride) {
+  const GroupOrder order = group_order(a.n_groups / ZR);
+  for (long long item = order.first; item < order.end; item += order.stride) {
     double dt;
-    const USeg S = find_seg(a, grp, seg, dt);
-    const long long lg = grp - S.first;
+    const USeg S = find_seg(a, item * ZR, seg, dt);
+    long long lg = item * ZR - S.first;  // the item's first group (local)
+    int gzs = 0;                          // groups between z neighbours
+    if constexpr (ZR > 1) {
+      // item -> (column c, run r) of the box; group (r ZR + j) nxy + c
+      const int nxy = S.ngx * S.ngy, li = (int)(item - S.first / ZR);
+      lg = (long long)(li / nxy) * ZR * nxy + li % nxy;
+      gzs = nxy;
+    }
+    const long long grp = S.first + lg;
     T* __restrict__ O = reinterpret_cast<T*>(S.out) + lg * 5 * 4096;
-    T* __restrict__ FO = S.flux ? reinterpret_cast<T*>(S.flux) + lg * 3 * a.nf * 5 * 256 : nullptr;
+    T* __restrict__ FO = (ZR == 1 && S.flux) ? reinterpret_cast<T*>(S.flux) + lg * 3 * a.nf * 5 * 256 : nullptr;
     ph.dtdh = (T)(dt / S.dh);
     ph.hdtdh = (T)(0.5 * dt / S.dh);
     // A segment that is no box in a launch that declared boxes only (its
@@ -154,13 +167,13 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
       wnext = src.load(-1 + zAhead);
     }
 
-    for (int t = -1; t <= 16; ++t) {
+    for (int t = -1; t <= nzt; ++t) {
       // ---- A: primitive planes t; z face states of plane t -----------------
       if (cross) {
         if (PPM) {
           put_plane(pcol, qcol, from_frame<2>(wa));
           V5<T> wc = to_frame<2>(MODE == 0 ? prim_of(wnext, ph) : wnext);  // plane t + 2
-          wnext = src.load(t + 1 + zAhead <= 16 + zAhead ? t + 1 + zAhead : 16 + zAhead);
+          wnext = src.load(t + 1 + zAhead <= nzt + zAhead ? t + 1 + zAhead : nzt + zAhead);
           V5<T> sn = slope(wa, wb, wc, ph);
           V5<T> ep = ppm_edge(wa, wb, st, sn);
           zfm = em;
@@ -170,7 +183,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
         } else {
           put_plane(pcol, qcol, from_frame<2>(wb));
           V5<T> wc = to_frame<2>(MODE == 0 ? prim_of(wnext, ph) : wnext);  // plane t + 1
-          wnext = src.load(t + 1 + zAhead <= 16 + zAhead ? t + 1 + zAhead : 16 + zAhead);
+          wnext = src.load(t + 1 + zAhead <= nzt + zAhead ? t + 1 + zAhead : nzt + zAhead);
           V5<T> s0 = slope(wa, wb, wc, ph);
           plm_faces(wa, wb, wc, s0, ph, zfm, zfp);
           wa = wb; wb = wc;
@@ -269,7 +282,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
         tally.fails(nf);
         zhp = zfp;
       }
-      if (t >= 0 && t <= 15) {
+      if (t >= 0 && t < nzt) {
         for (int q = NT - 1 - tid; q < 2 * kF2; q += NT) {
           const bool d = q >= kF2;
           const int r = d ? q - kF2 : q;
@@ -289,11 +302,14 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
         const int x = col.x, y = col.y;
         if (t >= 1) {
           V5<T> u = ucons(t - 1);
-          const int o = ((t - 1) * 16 + y) * 16 + x;
+          // plane t-1 lies in the item's group (t-1)/16, at its z = (t-1)%16
+          T* Og = O;
+          if constexpr (ZR > 1) Og += (long)((t - 1) >> 4) * gzs * (5 * 4096);
+          const int o = (((t - 1) & 15) * 16 + y) * 16 + x;
 #pragma unroll
-          for (int n = 0; n < 5; ++n) gstore(O + n * 4096, (unsigned)o * (unsigned)sizeof(T), u[n] - ph.dtdh * (acc[n] + hn[n]) + poison);
+          for (int n = 0; n < 5; ++n) gstore(Og + n * 4096, (unsigned)o * (unsigned)sizeof(T), u[n] - ph.dtdh * (acc[n] + hn[n]) + poison);
         }
-        if (t >= 0 && t <= 15) {
+        if (t >= 0 && t < nzt) {
           V5<T> fx = sub5(lds5(sF2, kF2, y * 17 + x + 1), lds5(sF2, kF2, y * 17 + x));
           V5<T> gy = from_frame<1>(sub5(lds5(sF2 + 5 * kF2, kF2, x * 17 + y + 1), lds5(sF2 + 5 * kF2, kF2, x * 17 + y)));
 #pragma unroll
@@ -306,7 +322,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
             for (int n = 0; n < 5; ++n) gstore(FO + ((2 * a.nf + f) * 5 + n) * 256, (unsigned)(y * 16 + x) * (unsigned)sizeof(T), hn[n] + poison);
           }
         }
-      } else if (FO && t >= 0 && t <= 15) {
+      } else if (FO && t >= 0 && t < nzt) {
         const int q = tid - 256;
         if (q < 2 * a.nf * 16) {
           const bool d = q >= a.nf * 16;

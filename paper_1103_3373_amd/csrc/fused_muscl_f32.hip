@@ -5,15 +5,27 @@
 
 namespace hy {
 
-template <int MODE, bool PPM, int RS, int WAVES, bool FAST>
-static hipError_t launch_one(const FusedArgs<float>& a, int grid, hipStream_t st) {
-  auto k = muscl::muscl_kernel<float, PPM, RS, WAVES, MODE, FAST>;
+template <int MODE, bool PPM, int RS, int WAVES, bool FAST, int ZR>
+static hipError_t launch_zr(const FusedArgs<float>& a, int grid, hipStream_t st) {
+  auto k = muscl::muscl_kernel<float, PPM, RS, WAVES, MODE, FAST, ZR>;
   const size_t shm = muscl::kLdsBytes(sizeof(float));
   static std::atomic<unsigned long long> lds_set{0};
   const hipError_t e = raise_lds_limit((const void*)k, shm, lds_set);
   if (e != hipSuccess) return e;
   k<<<dim3(grid), dim3(fz::kThreads), shm, st>>>(a);
   return hipGetLastError();
+}
+
+// Tile depths 2 and 4 exist for the PPM van Leer / characteristic
+// specialization with two workgroups per CU (zrun_built).
+template <int MODE, bool PPM, int RS, int WAVES, bool FAST>
+static hipError_t launch_one(const FusedArgs<float>& a, int grid, hipStream_t st) {
+  if constexpr (WAVES == 4 && FAST && PPM) {
+    if (a.zrun == 2) return launch_zr<MODE, PPM, RS, WAVES, FAST, 2>(a, grid, st);
+    if (a.zrun == 4) return launch_zr<MODE, PPM, RS, WAVES, FAST, 4>(a, grid, st);
+  }
+  if (a.zrun != 1) return hipErrorInvalidValue;
+  return launch_zr<MODE, PPM, RS, WAVES, FAST, 1>(a, grid, st);
 }
 
 template <int MODE, int WAVES, bool FAST>

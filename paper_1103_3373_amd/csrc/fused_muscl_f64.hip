@@ -7,7 +7,8 @@ namespace hy {
 
 template <int MODE, bool PPM, int RS, int WAVES, bool FAST>
 static hipError_t launch_one(const FusedArgs<double>& a, int grid, hipStream_t st) {
-  auto k = muscl::muscl_kernel<double, PPM, RS, WAVES, MODE, FAST>;
+  if (a.zrun != 1) return hipErrorInvalidValue;  // one group per work item in FP64
+  auto k = muscl::muscl_kernel<double, PPM, RS, WAVES, MODE, FAST, 1>;
   const size_t shm = muscl::kLdsBytes(sizeof(double));
   static std::atomic<unsigned long long> lds_set{0};
   const hipError_t e = raise_lds_limit((const void*)k, shm, lds_set);

@@ -84,12 +84,14 @@ struct FusedArgs {
   int zrun;
 };
 
-// Tile depths (groups per z-run) built for the CTU kernel: 1 always; 2 and
-// 4 for the FP32 specialization of the production configuration (van Leer
-// limiter on characteristic variables) with two workgroups per CU.
-inline bool ctu_zrun_built(bool f64, int waves, int limiter, int charlim, int zrun) {
+// Tile depths (groups per z-run) built for the fused kernels: 1 always; 2
+// and 4 for the FP32 specialization of the production configuration (van
+// Leer limiter on characteristic variables) with two workgroups per CU, for
+// CTU with PLM or PPM and for MHM / the VL second stage with PPM.
+inline bool zrun_built(int scheme, bool f64, int waves, int recon, int limiter, int charlim, int zrun) {
   if (zrun == 1) return true;
-  return !f64 && waves == 4 && limiter == 1 && charlim == 1 && (zrun == 2 || zrun == 4);
+  return !f64 && waves == 4 && limiter == 1 && charlim == 1 && (zrun == 2 || zrun == 4) &&
+         (scheme == 2 || recon == 1);
 }
 
 struct FusedCfg {

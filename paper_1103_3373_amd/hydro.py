@@ -381,7 +381,7 @@ def autotune(spec: Spec, n_groups_hint: int, stream=None) -> int:
 
 def set_launch_shape(spec: Spec, grid: int, variant: int, zrun: int = 0) -> None:
     """Pin the fused kernel's launch shape for spec's specialization
-    (grid 0 = default; variant 2 or 4; zrun = groups per z-run of a CTU box
+    (grid 0 = default; variant 2 or 4; zrun = groups per z-run of a box
     step, 0 = default; see hydro_set_launch_shape)."""
     _check("hydro_set_launch_shape", lib().hydro_set_launch_shape(ctypes.byref(spec), int(grid), int(variant),
                                                                   int(zrun)))

@@ -203,14 +203,14 @@ def test_noalloc_dt_rejects_sizes_before_device_calls(L):
 
 
 def test_box_launch_shape_defaults_and_pins():
-    """Host logic of the CTU box step's launch shape (no device work; the
+    """Host logic of a box step's launch shape (no device work; the
     compute-unit count is 256 on MI355X and the library's fallback without
     a device): the default tile depth is the largest of 4, 2 that divides
     the box's groups in z and leaves two runs per resident workgroup slot; a
     pinned depth that is not built or does not divide it falls back to the
     largest built divisor below it (depths 2 and 4 exist for the FP32 van
     Leer / characteristic specialization with two workgroups per CU only);
-    other schemes march one group at a time."""
+    MHM and VL (second stage) have runs with PPM only."""
     from paper_1103_3373_amd import hydro as H
     ctu = H.make_spec(H.CTU, H.PPM, H.HLLC, gamma=1.4, char=True)
     mhm = H.make_spec(H.MHM, H.PPM, H.HLLC, gamma=1.4, char=True)
@@ -231,8 +231,16 @@ def test_box_launch_shape_defaults_and_pins():
         H.set_launch_shape(f64, 0, 2, 0)
         minmod = H.make_spec(H.CTU, H.PPM, H.HLLC, H.GMINMOD, gamma=1.4, char=True)
         assert H.get_launch_shape(minmod, (256, 256, 256))[2] == 1
-        assert H.get_launch_shape(mhm, (256, 256, 256))[2] == 1
+        H.set_launch_shape(mhm, 0, 4, 0)
+        assert H.get_launch_shape(mhm, (256, 256, 256))[2] == 4  # MHM / VL with PPM have runs too
+        vl = H.make_spec(H.VL, H.PPM, H.HLLC, gamma=1.4, char=True)
+        assert H.get_launch_shape(vl, (256, 256, 256))[2] == 4
+        mhm_plm = H.make_spec(H.MHM, H.PLM, H.HLLC, gamma=1.4, char=True)
+        H.set_launch_shape(mhm_plm, 0, 4, 4)
+        assert H.get_launch_shape(mhm_plm, (256, 256, 256))[2] == 1  # not built
         with pytest.raises(H.HydroError):
             H.get_launch_shape(ctu, (256, 256, 250))
     finally:
         H.set_launch_shape(ctu, 0, 4, 0)
+        H.set_launch_shape(mhm, 0, 4, 0)
+        H.set_launch_shape(H.make_spec(H.MHM, H.PLM, H.HLLC, gamma=1.4, char=True), 0, 4, 0)
