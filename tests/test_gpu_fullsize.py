@@ -12,7 +12,8 @@ the group range), and the groups holding the largest pressure (blast
 regions).  At one tile depth (groups per z-run) results do not depend on
 the workgroup count or register variant (bit-identical); other tile depths
 agree to the FP32 parity bar.  The whole box conserves mass and energy to
-FP32 round-off."""
+FP32 round-off.  MHM and VL, the benchmark's side measurements, are checked
+on the same sampled groups at their default launch shape."""
 import numpy as np
 import pytest
 
@@ -122,3 +123,29 @@ def test_box_256_launch_shapes(case, grid, variant, zrun):
     ref, _ = O.solve_groups(Gs, 3, dt_dev.item(), 1.0 / N, GAMMA, O.CTU, O.PPM, O.HLLC, O.VANLEER, O.F_CHAR)
     l1, linf = rel_errors(out[pick].cpu().numpy(), ref)
     assert l1.max() <= 1e-5 and linf.max() <= 1e-5, (used, l1, linf)
+
+
+@pytest.mark.parametrize("scheme", ["MHM", "VL"])
+def test_box_256_mhm_vl_match_oracle(case, scheme):
+    """MHM and VL (PPM characteristic van Leer, HLLC, FP32) on the same 256^3
+    box in box mode with the default launch shape, as the benchmark's side
+    measurements run them (runs of four z-consecutive groups): the sampled
+    groups against the FP64 oracle on the same FP32-rounded input, relative
+    L1 and Linf <= 1e-5 per conserved variable, at CFL 0.3."""
+    H, box, state, _ = case
+    sc = {"MHM": (H.MHM, O.MHM), "VL": (H.VL, O.VL)}[scheme]
+    spec = H.make_spec(sc[0], H.PPM, H.HLLC, H.VANLEER, gamma=GAMMA, char=True)
+    assert H.get_launch_shape(spec, (N, N, N))[2] == 4
+    dt = O.cfl_dt(W.box_to_groups(box), 1.0 / N, GAMMA, 0.3)
+    dt_dev = torch.tensor([dt], dtype=torch.float64, device="cuda")
+    out = torch.empty_like(state)
+    H.step_box(state, out, (N, N, N), dt_dev, dh=1.0 / N, gamma=GAMMA, scheme=sc[0], recon=H.PPM, riemann=H.HLLC,
+               limiter=H.VANLEER, char=True)
+    torch.cuda.synchronize()
+    assert torch.isfinite(out).all().item()
+    g = H.ghost_width(sc[0], H.PPM)
+    pick = _sample(box)
+    Gs = np.stack([group_window(box, q, g) for q in pick])
+    ref, _ = O.solve_groups(Gs, g, dt, 1.0 / N, GAMMA, sc[1], O.PPM, O.HLLC, O.VANLEER, O.F_CHAR)
+    l1, linf = rel_errors(out[pick].cpu().numpy().astype(np.float64), ref)
+    assert l1.max() <= 1e-5 and linf.max() <= 1e-5, (scheme, l1, linf)
