@@ -7,6 +7,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <string>
@@ -267,6 +268,9 @@ int run_fused(const hy::Seg* segs_dev, int n_segs, long long n_groups, int g, in
   hy::FusedCfg cfg;
   cfg.grid = grid;
   cfg.waves = waves;
+  // The VL predictor takes one group per work item: as many workgroups as
+  // the second stage has groups in flight.
+  cfg.grid_pred = (int)std::min<long long>(n_groups, (long long)grid * zrun);
   hipError_t e = hy::launch_fused(a, scheme, recon, riemann, cfg, st);
   if (e != hipSuccess) return hip_fail(e, "fused solver launch");
   return 0;

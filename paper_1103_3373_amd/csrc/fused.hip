@@ -36,7 +36,7 @@ static hipError_t dispatch(const FusedArgs<T>& a, int scheme, int recon, int rie
   if (scheme == 0) return muscl(a, 0, recon, riemann, cfg, st);
   if (scheme == 1) {
     if (!a.wstar) return hipErrorInvalidValue;
-    hipError_t e = pred(a, recon, riemann, cfg.grid, st);
+    hipError_t e = pred(a, recon, riemann, cfg.grid_pred > 0 ? cfg.grid_pred : cfg.grid, st);
     if (e != hipSuccess) return e;
     return muscl(a, 1, recon, riemann, cfg, st);
   }

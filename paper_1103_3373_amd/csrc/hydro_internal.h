@@ -97,6 +97,8 @@ inline bool zrun_built(int scheme, bool f64, int waves, int recon, int limiter, 
 struct FusedCfg {
   int grid;          // number of workgroups (persistent)
   int waves;         // register budget variant: minimum waves per SIMD (2 or 4)
+  int grid_pred;     // VL predictor workgroups (0 = grid); it marches one group
+                     // at a time whatever the second stage's tile depth
 };
 
 bool fused_supported(int scheme, int recon, int riemann, int charlim);
