@@ -44,14 +44,15 @@ HY_DEV void face_values(const V5<T>& wm, const V5<T>& w0, const V5<T>& wp, const
   }
 }
 
-// Corrected state: U(W) - hdtdh * d, back to primitive with floors.
+// Corrected state: U(W) - hdtdh * d, back to primitive with floors; the
+// floor hits are counted for the whole wavefront (floor_wave).
 template <typename T>
-HY_DEV V5<T> correct(const V5<T>& W, const V5<T>& d, const Phys<T>& ph, int& floors) {
+HY_DEV V5<T> correct(const V5<T>& W, const V5<T>& d, const Phys<T>& ph, unsigned& wave_floors) {
   V5<T> u = cons_of(W, ph);
 #pragma unroll
   for (int n = 0; n < 5; ++n) u[n] -= ph.hdtdh * d[n];
   V5<T> w = prim_of(u, ph);
-  floors += floor_state(w, ph);
+  wave_floors += floor_wave(w, ph);
   return w;
 }
 

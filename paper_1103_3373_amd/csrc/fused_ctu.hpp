@@ -73,6 +73,13 @@ struct Tally {
   unsigned* c;  // [0] Roe fallbacks, [1] floor hits
   HY_DEV void fails(int v) const { if (v) atomicAdd(&c[0], (unsigned)v); }
   HY_DEV void floors(int v) const { if (v) atomicAdd(&c[1], (unsigned)v); }
+  // A wavefront's floor hits (uniform): one atomic from its first active lane.
+  HY_DEV void floors_wave(unsigned n) const {
+    if (n) {
+      const unsigned long long act = __builtin_amdgcn_ballot_w64(true);
+      if ((unsigned long long)__lane_id() == (unsigned long long)__builtin_ctzll(act)) atomicAdd(&c[1], n);
+    }
+  }
 };
 
 // Frame changes for a direction d known per lane (0 = x, whose frame is the
@@ -218,7 +225,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
         plm_faces(wb, w0, w1, sb, ph, ztm, ztp);
         ctu_trace<false>(w0, ztm, ztp, ph);
       }
-      tally.floors(floor_state(ztm, ph) + floor_state(ztp, ph));
+      tally.floors_wave(floor_wave(ztm, ph) + floor_wave(ztp, ph));
     }
 
     for (int t = -1; t <= nzt; ++t) {
@@ -249,11 +256,11 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
           ctu_trace<false>(w1, nzm, nzp, ph);
           w0 = w1; w1 = w3;
         }
-        const int fl = floor_state(nzm, ph) + floor_state(nzp, ph);
+        const unsigned fl = floor_wave(nzm, ph) + floor_wave(nzp, ph);
         int nf = 0;
         V5<T> h1p = riemann<RS>(ztp, nzm, ph, &nf);  // H1(t+1/2)
         if (live) {
-          tally.floors(fl);
+          tally.floors_wave(fl);
           tally.fails(nf);
         }
         if (t >= 0) sts5(sDH, kSQ, sqc, from_frame<2>(sub5(h1p, h1m)));
@@ -311,7 +318,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
                     fr);
         }
         ctu_trace<PPM>(wc, fl, fr, ph);
-        tally.floors(floor_state(fl, ph) + floor_state(fr, ph));
+        tally.floors_wave(floor_wave(fl, ph) + floor_wave(fr, ph));
         sts5(w, kSQ, r, fl);
         sts5(w + 5 * kSQ, kSQ, r, fr);
       }
@@ -345,10 +352,11 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
         V5<T> d;
 #pragma unroll
         for (int n = 0; n < 5; ++n) d[n] = fz_[n] + gz_[n];
-        int nfl = 0, nf = 0;
+        unsigned nfl = 0;
+        int nf = 0;
         V5<T> cm = correct(ztm, d, ph, nfl), cp = correct(ztp, d, ph, nfl);
         if (t >= 0) hn = from_frame<2>(riemann<RS>(zcp, cm, ph, &nf));  // H(t-1/2)
-        tally.floors(nfl);
+        tally.floors_wave(nfl);
         tally.fails(nf);
         zcp = cp;
       }
@@ -371,11 +379,12 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
 #pragma unroll
           for (int n = 0; n < 5; ++n) { dl[n] = ol[n] + Hl[n]; dr[n] = orr[n] + Hr[n]; }
           const int l = (b + 1) * 18 + (i + 1);
-          int nfl = 0, nf = 0;
+          unsigned nfl = 0;
+          int nf = 0;
           V5<T> L = correct(lds5(w + 5 * kSQ, kSQ, l), dl, ph, nfl);
           V5<T> R = correct(lds5(w, kSQ, l + 1), dr, ph, nfl);
           sts5(sF2 + (d ? 5 * kF2 : 0), kF2, r, riemann<RS>(L, R, ph, &nf));
-          tally.floors(nfl);
+          tally.floors_wave(nfl);
           tally.fails(nf);
         }
       }

@@ -188,7 +188,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
           plm_faces(wa, wb, wc, s0, ph, zfm, zfp);
           wa = wb; wb = wc;
         }
-        tally.floors(floor_state(zfm, ph) + floor_state(zfp, ph));
+        tally.floors_wave(floor_wave(zfm, ph) + floor_wave(zfp, ph));
       } else if (col.active) {
         put_plane(pcol, qcol, wprim(t));
       }
@@ -232,7 +232,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
           plm_faces(lds5(pl, kP, c - 1), wc, lds5(pl, kP, c + 1), lds5(ss, kS, (b + 1) * 20 + (aa + 2)), ph, fl,
                     fr);
         }
-        tally.floors(floor_state(fl, ph) + floor_state(fr, ph));
+        tally.floors_wave(floor_wave(fl, ph) + floor_wave(fr, ph));
         sts5(w, kSQ, r, fl);
         sts5(w + 5 * kSQ, kSQ, r, fr);
       }
@@ -262,14 +262,14 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
             for (int n = 0; n < 5; ++n) dU[n] += fp[n] - fm[n];
           }
           V5<T> dx = to_frame<0>(dU), dy = to_frame<1>(dU), dz = to_frame<2>(dU);
-          int nfl = 0;
+          unsigned nfl = 0;
           sts5(wx, kSQ, sqx, correct(xm, dx, ph, nfl));
           sts5(wx + 5 * kSQ, kSQ, sqx, correct(xp, dx, ph, nfl));
           sts5(wy, kSQ, sqy, correct(ym, dy, ph, nfl));
           sts5(wy + 5 * kSQ, kSQ, sqy, correct(yp, dy, ph, nfl));
           zfm = correct(zfm, dz, ph, nfl);
           zfp = correct(zfp, dz, ph, nfl);
-          tally.floors(nfl);
+          tally.floors_wave(nfl);
         }
         __syncthreads();
       }

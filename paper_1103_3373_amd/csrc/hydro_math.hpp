@@ -136,6 +136,18 @@ template <typename T> HY_DEV int floor_state(V5<T>& W, const Phys<T>& ph) {
   return h;
 }
 
+// The same floors with the hits counted for the whole wavefront: the compare
+// masks of the active lanes are popcounted by scalar instructions, so the
+// per-lane cost is the clamp's two compares and two selects.  Returns the
+// wavefront's number of hits (uniform across its lanes).
+template <typename T> HY_DEV unsigned floor_wave(V5<T>& W, const Phys<T>& ph) {
+  const bool l0 = W[0] < ph.floor, l4 = W[4] < ph.floor;
+  W[0] = l0 ? ph.floor : W[0];
+  W[4] = l4 ? ph.floor : W[4];
+  return (unsigned)(__builtin_popcountll(__builtin_amdgcn_ballot_w64(l0)) +
+                    __builtin_popcountll(__builtin_amdgcn_ballot_w64(l4)));
+}
+
 // ---- limiters -----------------------------------------------------------------
 // 0 generalized minmod (theta), 1 van Leer, 2 van Albada, 3 hybrid (van Leer
 // bounded by generalized minmod).  Zero at extrema.
