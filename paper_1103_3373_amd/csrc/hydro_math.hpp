@@ -299,8 +299,42 @@ HY_DEV void ctu_trace(const V5<T>& w, V5<T>& fl, V5<T>& fr, const Phys<T>& ph) {
   V5<T> da = char_L(w, c, ic, ic2, dw);
   V5<T> a6;
   if (PPM) a6 = char_L(w, c, ic, ic2, w6);
-  V5<T> L, R;
   const T two3 = T(2) / T(3);
+  if constexpr (FastMath<T>::on) {
+    // FP32: the reference-state extrapolation and the correction of the
+    // waves that reach a face add up, wave by wave, to one coefficient.  With
+    // sigma the wave's own speed when it reaches the face and the reference
+    // speed (sM right, sm left) otherwise, the right face gets
+    //   fr - R [sigma/2 (da - (1 - 2/3 sigma) a6)]
+    // and the left face fl - R [sigma/2 (da + (1 + 2/3 sigma) a6)]: the same
+    // states as the form below (R L = I), with one expansion per face.
+    const T sk[3] = {s[0], s[1], s[4]};
+    T hp[3], gp[3], hm[3], gm[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const T sp = sk[k] > T(0) ? sk[k] : sM;
+      const T sn = sk[k] < T(0) ? sk[k] : sm;
+      hp[k] = T(0.5) * sp;
+      hm[k] = T(0.5) * sn;
+      gp[k] = T(1) - two3 * sp;
+      gm[k] = T(1) + two3 * sn;
+    }
+    V5<T> cp, cm;
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+      const int k = a == 0 ? 0 : (a == 4 ? 2 : 1);
+      cp[a] = hp[k] * (PPM ? da[a] - gp[k] * a6[a] : da[a]);
+      cm[a] = hm[k] * (PPM ? da[a] + gm[k] * a6[a] : da[a]);
+    }
+    const V5<T> eR = char_R(w, c, ir, cp), eL = char_R(w, c, ir, cm);
+#pragma unroll
+    for (int n = 0; n < 5; ++n) {
+      fr[n] -= eR[n];
+      fl[n] -= eL[n];
+    }
+    return;
+  }
+  V5<T> L, R;
 #pragma unroll
   for (int n = 0; n < 5; ++n) {
     T t6p = PPM ? (T(1) - two3 * sM) * w6[n] : T(0);
