@@ -210,8 +210,8 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
         w0 = zprim(-1);
         w1 = zprim(0);
         w2 = zprim(1);
-        V5<T> sa = slope(wa, wb, w0, ph), sb = slope(wb, w0, w1, ph);
-        s1 = slope(w0, w1, w2, ph);
+        V5<T> sa = slope<PPM>(wa, wb, w0, ph), sb = slope<PPM>(wb, w0, w1, ph);
+        s1 = slope<PPM>(w0, w1, w2, ph);
         ztm = ppm_edge(wb, w0, sa, sb);
         e0 = ppm_edge(w0, w1, sb, s1);
         ztp = e0;
@@ -221,7 +221,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
         V5<T> wb = zprim(-2);
         w0 = zprim(-1);
         w1 = zprim(0);
-        V5<T> sb = slope(wb, w0, w1, ph);
+        V5<T> sb = slope<PPM>(wb, w0, w1, ph);
         plm_faces(wb, w0, w1, sb, ph, ztm, ztp);
         ctu_trace<false>(w0, ztm, ztp, ph);
       }
@@ -242,7 +242,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
         const bool live = t < nzt;
         if (PPM) {
           V5<T> w3 = zprim(live ? t + 3 : t + 2);
-          V5<T> s2 = slope(w1, w2, w3, ph);
+          V5<T> s2 = slope<PPM>(w1, w2, w3, ph);
           V5<T> e1 = ppm_edge(w1, w2, s1, s2);
           nzm = e0;
           nzp = e1;
@@ -251,7 +251,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
           w0 = w1; w1 = w2; w2 = w3; s1 = s2; e0 = e1;
         } else {
           V5<T> w3 = zprim(live ? t + 2 : t + 1);
-          V5<T> sb = slope(w0, w1, w3, ph);
+          V5<T> sb = slope<PPM>(w0, w1, w3, ph);
           plm_faces(w0, w1, w3, sb, ph, nzm, nzp);
           ctu_trace<false>(w1, nzm, nzp, ph);
           w0 = w1; w1 = w3;
@@ -286,7 +286,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
         const int aa = r % wS + a0S, b = r / wS - 1;
         const T* pl = d ? sQ : sP;
         const int c = (b + G) * N + (aa + G);
-        V5<T> s = slope(lds5(pl, kP, c - 1), lds5(pl, kP, c), lds5(pl, kP, c + 1), ph);
+        V5<T> s = slope<PPM>(lds5(pl, kP, c - 1), lds5(pl, kP, c), lds5(pl, kP, c + 1), ph);
         sts5(sS + (d ? 5 * kS : 0), kS, (b + 1) * 20 + (aa + 2), s);
       }
       __syncthreads();

@@ -157,8 +157,8 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
         V5<T> w3 = zprim(-3), w2 = zprim(-2);
         wa = zprim(-1);
         wb = zprim(0);
-        V5<T> s2 = slope(w3, w2, wa, ph);
-        st = slope(w2, wa, wb, ph);
+        V5<T> s2 = slope<PPM>(w3, w2, wa, ph);
+        st = slope<PPM>(w2, wa, wb, ph);
         em = ppm_edge(w2, wa, s2, st);
       } else {
         wa = zprim(-2);
@@ -174,7 +174,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
           put_plane(pcol, qcol, from_frame<2>(wa));
           V5<T> wc = to_frame<2>(MODE == 0 ? prim_of(wnext, ph) : wnext);  // plane t + 2
           wnext = src.load(t + 1 + zAhead <= nzt + zAhead ? t + 1 + zAhead : nzt + zAhead);
-          V5<T> sn = slope(wa, wb, wc, ph);
+          V5<T> sn = slope<PPM>(wa, wb, wc, ph);
           V5<T> ep = ppm_edge(wa, wb, st, sn);
           zfm = em;
           zfp = ep;
@@ -184,7 +184,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
           put_plane(pcol, qcol, from_frame<2>(wb));
           V5<T> wc = to_frame<2>(MODE == 0 ? prim_of(wnext, ph) : wnext);  // plane t + 1
           wnext = src.load(t + 1 + zAhead <= nzt + zAhead ? t + 1 + zAhead : nzt + zAhead);
-          V5<T> s0 = slope(wa, wb, wc, ph);
+          V5<T> s0 = slope<PPM>(wa, wb, wc, ph);
           plm_faces(wa, wb, wc, s0, ph, zfm, zfp);
           wa = wb; wb = wc;
         }
@@ -201,7 +201,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) muscl_kernel(FusedArgs<T> a) 
         const int aa = r % wS + a0S, b = r / wS - 1;
         const T* pl = d ? sQ : sP;
         const int c = (b + G) * N + (aa + G);
-        V5<T> s = slope(lds5(pl, kP, c - 1), lds5(pl, kP, c), lds5(pl, kP, c + 1), ph);
+        V5<T> s = slope<PPM>(lds5(pl, kP, c - 1), lds5(pl, kP, c), lds5(pl, kP, c + 1), ph);
         sts5(sS + (d ? 5 * kS : 0), kS, (b + 1) * 20 + (aa + 2), s);
       }
       __syncthreads();

@@ -99,12 +99,12 @@ HY_DEV Box3 plain_faces(const PlainCtx<T>& c, const T* Wsrc, Box3 wr, const Phys
     if (PPM) {
       V5<T> wmm = to_frame<D>(ld(Wsrc, c.nc, q - 2 * s));
       V5<T> wpp = to_frame<D>(ld(Wsrc, c.nc, q + 2 * s));
-      V5<T> sm = slope(wmm, wm, w0, ph), s0 = slope(wm, w0, wp, ph), sp = slope(w0, wp, wpp, ph);
+      V5<T> sm = slope<PPM>(wmm, wm, w0, ph), s0 = slope<PPM>(wm, w0, wp, ph), sp = slope<PPM>(w0, wp, wpp, ph);
       fl = ppm_edge(wm, w0, sm, s0);
       fr2 = ppm_edge(w0, wp, s0, sp);
       ppm_mono(w0, fl, fr2);
     } else {
-      V5<T> s0 = slope(wm, w0, wp, ph);
+      V5<T> s0 = slope<PPM>(wm, w0, wp, ph);
       plm_faces(wm, w0, wp, s0, ph, fl, fr2);
     }
     if (TRACE) ctu_trace<PPM>(w0, fl, fr2, ph);
