@@ -180,12 +180,20 @@ template <typename T> HY_DEV T limit(T dl, T dr, const Phys<T>& ph, T ks = T(1))
 template <typename T> HY_DEV V5<T> char_L(const V5<T>& W, T c, T ic, T ic2, const V5<T>& dw) {
   V5<T> a;
   T rc = T(0.5) * W[0] * ic;
-  T pc = T(0.5) * dw[4] * ic2;
-  a[0] = pc - rc * dw[1];
-  a[1] = dw[0] - dw[4] * ic2;
+  if constexpr (FastMath<T>::on) {
+    // FP32: the density wave from the acoustic term (dw0 - dp/c^2 = dw0 - 2 pc)
+    T pc = dw[4] * (T(0.5) * ic2);
+    a[0] = pc - rc * dw[1];
+    a[1] = dw[0] - T(2) * pc;
+    a[4] = pc + rc * dw[1];
+  } else {
+    T pc = T(0.5) * dw[4] * ic2;
+    a[0] = pc - rc * dw[1];
+    a[1] = dw[0] - dw[4] * ic2;
+    a[4] = pc + rc * dw[1];
+  }
   a[2] = dw[2];
   a[3] = dw[3];
-  a[4] = pc + rc * dw[1];
   return a;
 }
 template <typename T> HY_DEV V5<T> char_R(const V5<T>& W, T c, T ir, const V5<T>& a) {
@@ -302,15 +310,6 @@ HY_DEV void ctu_trace(const V5<T>& w, V5<T>& fl, V5<T>& fr, const Phys<T>& ph) {
   s[4] = (w[1] + c) * ph.dtdh;
   T sM = vmax(s[4], T(0));
   T sm = vmin(s[0], T(0));
-  V5<T> dw, w6;
-#pragma unroll
-  for (int n = 0; n < 5; ++n) {
-    dw[n] = fr[n] - fl[n];
-    w6[n] = PPM ? T(6) * (w[n] - T(0.5) * (fl[n] + fr[n])) : T(0);
-  }
-  V5<T> da = char_L(w, c, ic, ic2, dw);
-  V5<T> a6;
-  if (PPM) a6 = char_L(w, c, ic, ic2, w6);
   const T two3 = T(2) / T(3);
   if constexpr (FastMath<T>::on) {
     // FP32: the reference-state extrapolation and the correction of the
@@ -319,7 +318,18 @@ HY_DEV void ctu_trace(const V5<T>& w, V5<T>& fl, V5<T>& fr, const Phys<T>& ph) {
     // speed (sM right, sm left) otherwise, the right face gets
     //   fr - R [sigma/2 (da - (1 - 2/3 sigma) a6)]
     // and the left face fl - R [sigma/2 (da + (1 + 2/3 sigma) a6)]: the same
-    // states as the form below (R L = I), with one expansion per face.
+    // states as the form below (R L = I), with one expansion per face.  The
+    // parabola amplitudes are projected as a sixth of themselves,
+    // L (w - (fl + fr)/2), and their factors carry the 6.
+    V5<T> dw, wc;
+#pragma unroll
+    for (int n = 0; n < 5; ++n) {
+      dw[n] = fr[n] - fl[n];
+      wc[n] = PPM ? w[n] - T(0.5) * (fl[n] + fr[n]) : T(0);
+    }
+    const V5<T> da = char_L(w, c, ic, ic2, dw);
+    V5<T> a6;
+    if (PPM) a6 = char_L(w, c, ic, ic2, wc);
     const T sk[3] = {s[0], s[1], s[4]};
     T hp[3], gp[3], hm[3], gm[3];
 #pragma unroll
@@ -328,8 +338,8 @@ HY_DEV void ctu_trace(const V5<T>& w, V5<T>& fl, V5<T>& fr, const Phys<T>& ph) {
       const T sn = sk[k] < T(0) ? sk[k] : sm;
       hp[k] = T(0.5) * sp;
       hm[k] = T(0.5) * sn;
-      gp[k] = T(1) - two3 * sp;
-      gm[k] = T(1) + two3 * sn;
+      gp[k] = T(6) - T(4) * sp;
+      gm[k] = T(6) + T(4) * sn;
     }
     V5<T> cp, cm;
 #pragma unroll
@@ -346,6 +356,15 @@ HY_DEV void ctu_trace(const V5<T>& w, V5<T>& fl, V5<T>& fr, const Phys<T>& ph) {
     }
     return;
   }
+  V5<T> dw, w6;
+#pragma unroll
+  for (int n = 0; n < 5; ++n) {
+    dw[n] = fr[n] - fl[n];
+    w6[n] = PPM ? T(6) * (w[n] - T(0.5) * (fl[n] + fr[n])) : T(0);
+  }
+  V5<T> da = char_L(w, c, ic, ic2, dw);
+  V5<T> a6;
+  if (PPM) a6 = char_L(w, c, ic, ic2, w6);
   V5<T> L, R;
 #pragma unroll
   for (int n = 0; n < 5; ++n) {
