@@ -304,12 +304,6 @@ HY_DEV void ctu_trace(const V5<T>& w, V5<T>& fl, V5<T>& fr, const Phys<T>& ph) {
   T c, ic;
   sound_pair(w, ir, ph, c, ic);
   T ic2 = ic * ic;
-  T s[5];
-  s[0] = (w[1] - c) * ph.dtdh;
-  s[1] = w[1] * ph.dtdh;
-  s[4] = (w[1] + c) * ph.dtdh;
-  T sM = vmax(s[4], T(0));
-  T sm = vmin(s[0], T(0));
   const T two3 = T(2) / T(3);
   if constexpr (FastMath<T>::on) {
     // FP32: the reference-state extrapolation and the correction of the
@@ -319,8 +313,14 @@ HY_DEV void ctu_trace(const V5<T>& w, V5<T>& fl, V5<T>& fr, const Phys<T>& ph) {
     //   fr - R [sigma/2 (da - (1 - 2/3 sigma) a6)]
     // and the left face fl - R [sigma/2 (da + (1 + 2/3 sigma) a6)]: the same
     // states as the form below (R L = I), with one expansion per face.  The
+    // speeds are formed as halves, h = sigma/2 = lambda dt/(2 dh); the
     // parabola amplitudes are projected as a sixth of themselves,
-    // L (w - (fl + fr)/2), and their factors carry the 6.
+    // L (w - (fl + fr)/2), and their factors (6 - 8h, 6 + 8h) carry the 6.
+    // The slowest wave reaches the left face only with its own speed or sm,
+    // which is min(its speed, 0) = sm; likewise the fastest on the right.
+    // (u -+ c) first: its sign decides the switch at lambda = 0 exactly.
+    const T uh = w[1] * ph.hdtdh, h0 = (w[1] - c) * ph.hdtdh, h4 = (w[1] + c) * ph.hdtdh;
+    const T hM = vmax(h4, T(0)), hm0 = vmin(h0, T(0));
     V5<T> dw, wc;
 #pragma unroll
     for (int n = 0; n < 5; ++n) {
@@ -330,16 +330,17 @@ HY_DEV void ctu_trace(const V5<T>& w, V5<T>& fl, V5<T>& fr, const Phys<T>& ph) {
     const V5<T> da = char_L(w, c, ic, ic2, dw);
     V5<T> a6;
     if (PPM) a6 = char_L(w, c, ic, ic2, wc);
-    const T sk[3] = {s[0], s[1], s[4]};
     T hp[3], gp[3], hm[3], gm[3];
+    hp[0] = h0 > T(0) ? h0 : hM;
+    hp[1] = uh > T(0) ? uh : hM;
+    hp[2] = hM;
+    hm[0] = hm0;
+    hm[1] = uh < T(0) ? uh : hm0;
+    hm[2] = h4 < T(0) ? h4 : hm0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const T sp = sk[k] > T(0) ? sk[k] : sM;
-      const T sn = sk[k] < T(0) ? sk[k] : sm;
-      hp[k] = T(0.5) * sp;
-      hm[k] = T(0.5) * sn;
-      gp[k] = T(6) - T(4) * sp;
-      gm[k] = T(6) + T(4) * sn;
+      gp[k] = T(6) - T(8) * hp[k];
+      gm[k] = T(6) + T(8) * hm[k];
     }
     V5<T> cp, cm;
 #pragma unroll
@@ -356,6 +357,12 @@ HY_DEV void ctu_trace(const V5<T>& w, V5<T>& fl, V5<T>& fr, const Phys<T>& ph) {
     }
     return;
   }
+  T s[5];
+  s[0] = (w[1] - c) * ph.dtdh;
+  s[1] = w[1] * ph.dtdh;
+  s[4] = (w[1] + c) * ph.dtdh;
+  T sM = vmax(s[4], T(0));
+  T sm = vmin(s[0], T(0));
   V5<T> dw, w6;
 #pragma unroll
   for (int n = 0; n < 5; ++n) {
