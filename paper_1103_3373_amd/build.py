@@ -26,14 +26,13 @@ CFLAGS = [
 ]
 # Per-file additions.  The CTU kernels build with the AMDGPU scheduler's
 # register-pressure trackers that follow the register allocator's own
-# accounting (31 -> 20 spilled VGPRs and about 2% faster for CTU+PPM+HLLC;
-# measured slower for the MHM/VL kernel, so not used there).  The FP32
-# HLLC/HLLE instantiations also use the max-ILP scheduling strategy (20 -> 13
-# spilled VGPRs, about 6% faster for CTU+PPM+HLLC); it made the Roe
-# instantiations about 3% slower and the MHM/VL kernel no faster, so those
-# keep the default strategy.
+# accounting (measured slower for the MHM/VL kernel, so not used there).  For
+# the FP32 HLLC/HLLE CTU kernel of the current source they give 1 spilled
+# VGPR and 1.150 ms at 256^3, against 30 and 1.186 ms with the default
+# scheduler; adding the max-ILP strategy (which once paid off for this file)
+# now gives 26 spills and 1.154 ms, and max-ILP alone 1.272 ms.
 EXTRA = {
-    "fused_ctu_f32.hip": ["-mllvm", "-amdgpu-use-amdgpu-trackers=1", "-mllvm", "-amdgpu-sched-strategy=max-ilp"],
+    "fused_ctu_f32.hip": ["-mllvm", "-amdgpu-use-amdgpu-trackers=1"],
     "fused_ctu_f32_roe.hip": ["-mllvm", "-amdgpu-use-amdgpu-trackers=1"],
     "fused_ctu_f64.hip": ["-mllvm", "-amdgpu-use-amdgpu-trackers=1"],
 }
