@@ -1,56 +1,16 @@
-// Instantiations of the fused MHM / VL-second-stage kernel and the VL
-// predictor for float.
-#include "fused_muscl.hpp"
+// Instantiations of the fused VL-second-stage kernel and the VL predictor for
+// float; MHM's are in their own file (other scheduler options).
+#include "fused_muscl_launch.hpp"
 #include "fused_vlpred.hpp"
 
 namespace hy {
 
-template <int MODE, bool PPM, int RS, int WAVES, bool FAST, int ZR>
-static hipError_t launch_zr(const FusedArgs<float>& a, int grid, hipStream_t st) {
-  auto k = muscl::muscl_kernel<float, PPM, RS, WAVES, MODE, FAST, ZR>;
-  const size_t shm = muscl::kLdsBytes(sizeof(float));
-  static std::atomic<unsigned long long> lds_set{0};
-  const hipError_t e = raise_lds_limit((const void*)k, shm, lds_set);
-  if (e != hipSuccess) return e;
-  k<<<dim3(grid), dim3(fz::kThreads), shm, st>>>(a);
-  return hipGetLastError();
-}
-
-// Tile depths 2 and 4 exist for the PPM van Leer / characteristic
-// specialization with two workgroups per CU (zrun_built).
-template <int MODE, bool PPM, int RS, int WAVES, bool FAST>
-static hipError_t launch_one(const FusedArgs<float>& a, int grid, hipStream_t st) {
-  if constexpr (WAVES == 4 && FAST && PPM) {
-    if (a.zrun == 2) return launch_zr<MODE, PPM, RS, WAVES, FAST, 2>(a, grid, st);
-    if (a.zrun == 4) return launch_zr<MODE, PPM, RS, WAVES, FAST, 4>(a, grid, st);
-  }
-  if (a.zrun != 1) return hipErrorInvalidValue;
-  return launch_zr<MODE, PPM, RS, WAVES, FAST, 1>(a, grid, st);
-}
-
-template <int MODE, int WAVES, bool FAST>
-static hipError_t launch_wf(const FusedArgs<float>& a, int recon, int riemann, int grid, hipStream_t st) {
-  if (recon == 1) {
-    if (riemann == 0) return launch_one<MODE, true, 0, WAVES, FAST>(a, grid, st);
-    if (riemann == 1) return launch_one<MODE, true, 1, WAVES, FAST>(a, grid, st);
-    return launch_one<MODE, true, 2, WAVES, FAST>(a, grid, st);
-  }
-  if (riemann == 0) return launch_one<MODE, false, 0, WAVES, FAST>(a, grid, st);
-  if (riemann == 1) return launch_one<MODE, false, 1, WAVES, FAST>(a, grid, st);
-  return launch_one<MODE, false, 2, WAVES, FAST>(a, grid, st);
-}
-
-template <int MODE, int WAVES>
-static hipError_t launch_w(const FusedArgs<float>& a, int recon, int riemann, int grid, hipStream_t st) {
-  if (a.limiter == 1 && a.charlim == 1) return launch_wf<MODE, WAVES, true>(a, recon, riemann, grid, st);
-  return launch_wf<MODE, WAVES, false>(a, recon, riemann, grid, st);
-}
+hipError_t launch_mhm_f32(const FusedArgs<float>& a, int recon, int riemann, const FusedCfg& cfg, hipStream_t st);
 
 hipError_t launch_muscl_f32(const FusedArgs<float>& a, int mode, int recon, int riemann, const FusedCfg& cfg,
                              hipStream_t st) {
-  if (cfg.waves == 4)
-    return mode == 0 ? launch_w<0, 4>(a, recon, riemann, cfg.grid, st) : launch_w<1, 4>(a, recon, riemann, cfg.grid, st);
-  return mode == 0 ? launch_w<0, 2>(a, recon, riemann, cfg.grid, st) : launch_w<1, 2>(a, recon, riemann, cfg.grid, st);
+  if (mode == 0) return launch_mhm_f32(a, recon, riemann, cfg, st);
+  return muscl_launch::launch_mode<1>(a, recon, riemann, cfg, st);
 }
 
 template <int G, int RS>
