@@ -39,7 +39,9 @@ EXTRA = {
     # the VL step 1% slower.
     "fused_muscl_f32.hip": ["-mllvm", "-amdgpu-use-amdgpu-trackers=1"],
     "fused_muscl_f32_mhm.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
-    "fused_ctu_f32_roe.hip": ["-mllvm", "-amdgpu-use-amdgpu-trackers=1"],
+    # The FP32 Roe CTU file (fused_ctu_f32_roe.hip) builds with the default
+    # scheduler: 1.456 ms per 256^3 box step against 1.504 ms with the
+    # trackers and 1.549 ms with max-ILP.
     "fused_ctu_f64.hip": ["-mllvm", "-amdgpu-use-amdgpu-trackers=1"],
 }
 
