@@ -202,6 +202,12 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
     V5<T> h1m;          // H1(t-1/2)
     V5<T> zcp;          // corrected right state of plane t-1
     V5<T> acc;          // flux differences of the plane being updated, all but its upper z face (lab)
+    // The plane that enters the window next (t + ahead in iteration t) is
+    // requested one plane early, so its load overlaps a whole iteration; the
+    // last plane a column reads is zlast (the last iteration repeats it).
+    V5<T> unext;        // conserved state of that plane
+    constexpr int ahead = PPM ? 3 : 2;
+    const int zlast = nzt + ahead - 1;
 
     // ---- prologue: window and traced states of plane -1 -------------------
     if (cross) {
@@ -210,6 +216,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
         w0 = zprim(-1);
         w1 = zprim(0);
         w2 = zprim(1);
+        unext = load_cons(-1 + ahead);
         V5<T> sa = slope<PPM>(wa, wb, w0, ph), sb = slope<PPM>(wb, w0, w1, ph);
         s1 = slope<PPM>(w0, w1, w2, ph);
         ztm = ppm_edge(wb, w0, sa, sb);
@@ -221,6 +228,7 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
         V5<T> wb = zprim(-2);
         w0 = zprim(-1);
         w1 = zprim(0);
+        unext = load_cons(-1 + ahead);
         V5<T> sb = slope<PPM>(wb, w0, w1, ph);
         plm_faces(wb, w0, w1, sb, ph, ztm, ztp);
         ctu_trace<false>(w0, ztm, ztp, ph);
@@ -240,8 +248,9 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
         // window advances the same way on every iteration (no copies at a
         // join); its diagnostics are not counted and its results are unused.
         const bool live = t < nzt;
+        const V5<T> w3 = to_frame<2>(prim_of(unext, ph));  // plane min(t + ahead, zlast)
+        unext = load_cons(t + 1 + ahead < zlast ? t + 1 + ahead : zlast);
         if (PPM) {
-          V5<T> w3 = zprim(live ? t + 3 : t + 2);
           V5<T> s2 = slope<PPM>(w1, w2, w3, ph);
           V5<T> e1 = ppm_edge(w1, w2, s1, s2);
           nzm = e0;
@@ -250,7 +259,6 @@ __global__ void __launch_bounds__(kThreads, WAVES) ctu_fused_kernel(FusedArgs<T>
           ctu_trace<true>(w1, nzm, nzp, ph);
           w0 = w1; w1 = w2; w2 = w3; s1 = s2; e0 = e1;
         } else {
-          V5<T> w3 = zprim(live ? t + 2 : t + 1);
           V5<T> sb = slope<PPM>(w0, w1, w3, ph);
           plm_faces(w0, w1, w3, sb, ph, nzm, nzp);
           ctu_trace<false>(w1, nzm, nzp, ph);
