@@ -208,7 +208,7 @@ template <typename T> HY_DEV V5<T> char_R(const V5<T>& W, T c, T ir, const V5<T>
 
 // Limited slope of the middle cell (frame states).  PPM uses a slope only in
 // the edge formula, divided by 6; in FP32 the slopes of PPM are carried
-// already divided by 6 (slope_div), which folds the division into the
+// already divided by 6 (SlopeScale::div6), which folds the division into the
 // limiter's own multiplication (van Leer's factor 2 becomes 1/3) and saves
 // an operation per component and edge.  FP64 and PLM carry the slope.
 template <bool PPM, typename T> struct SlopeScale {
