@@ -244,3 +244,17 @@ def test_box_launch_shape_defaults_and_pins():
         H.set_launch_shape(ctu, 0, 4, 0)
         H.set_launch_shape(mhm, 0, 4, 0)
         H.set_launch_shape(H.make_spec(H.MHM, H.PLM, H.HLLC, gamma=1.4, char=True), 0, 4, 0)
+
+
+def test_counter_profile_matches_kernel_sources():
+    """The committed rocprofv3 counter summary of the benchmarked CTU kernel
+    was taken on the current kernel sources, so bench.py reports the measured
+    HBM traffic (roofline.traffic) instead of null; a change to those sources
+    needs a new counter run."""
+    import importlib.util
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_for_test", os.path.join(root, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    traffic = bench.traffic_from_profile(bench.kernel_source_hash())
+    assert traffic is not None and traffic > 0.671e9  # at least the algorithmic bytes
