@@ -47,6 +47,23 @@ def scaled_max_err(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
+def var_max_err(a, b):
+    """Largest per-variable max |a-b| of states a against reference b, each
+    variable against its own scale: max |rho| for mass, max |E| for energy,
+    and the reference's largest momentum magnitude |m| for the three momentum
+    components (so a component that is near zero everywhere is not measured
+    against the energy).  States grouped [n, 5, ...] or box [5, ...]."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    ax = 1 if a.ndim == 5 else 0
+    a = np.moveaxis(a, ax, 0).reshape(5, -1)
+    b = np.moveaxis(b, ax, 0).reshape(5, -1)
+    d = np.abs(a - b).max(axis=1)
+    mag = np.sqrt((b[1:4] ** 2).sum(0)).max()
+    scale = np.array([np.abs(b[0]).max(), mag, mag, mag, np.abs(b[4]).max()])
+    return float((d / np.maximum(scale, 1e-300)).max())
+
+
 def field_errors(a, b):
     """Per-variable (L1, Linf) error of state a against reference b, both
     grouped [n, 5, 16, 16, 16] or box [5, ...].  Mass and energy errors are

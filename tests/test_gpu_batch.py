@@ -14,7 +14,7 @@ import pytest
 
 import oracle as O
 from paper_1103_3373_amd import workloads as W
-from tests._util import rel_errors, random_smooth_box, scaled_max_err
+from tests._util import rel_errors, random_smooth_box, scaled_max_err, var_max_err
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -140,6 +140,7 @@ def test_step_box_equals_fill_and_solve(H, scheme, recon, rs, char, dtype):
     got = W.groups_to_box(out_box.cpu().numpy().astype(np.float64), nx, ny, nz)
     if dtype == torch.float64:
         assert scaled_max_err(got, ref) <= 1e-12
+        assert var_max_err(got, ref) <= 1e-12
     else:
         l1, _ = rel_errors(got, ref)
         assert l1.max() <= 1e-5

@@ -14,7 +14,7 @@ import pytest
 
 import oracle as O
 from paper_1103_3373_amd import workloads as W
-from tests._util import random_smooth_box, rel_errors, scaled_max_err
+from tests._util import random_smooth_box, rel_errors, scaled_max_err, var_max_err
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -61,6 +61,7 @@ def test_fp64_one_step_matches_oracle(H, scheme, recon, rs, char, plain):
     ref, rflux = O.solve_groups(G, g, dt, dh, gamma, scheme, recon, rs, 1, flags, want_flux=True)
     out, flux = _run(H, G, g, torch.float64, dt, dh, gamma, scheme, recon, rs, 1, char, plain, flux_mid=True)
     assert scaled_max_err(out, ref) <= 1e-12
+    assert var_max_err(out, ref) <= 1e-12
     assert scaled_max_err(flux, rflux) <= 1e-12
 
 
@@ -75,6 +76,7 @@ def test_fp64_limiters(H, lim, scheme, recon, char):
     for plain in (True, False):
         out, _ = _run(H, G, g, torch.float64, 3e-3, 1 / 32, gamma, scheme, recon, 0, lim, char, plain, False)
         assert scaled_max_err(out, ref) <= 1e-12
+        assert var_max_err(out, ref) <= 1e-12
 
 
 @pytest.mark.parametrize("scheme,recon,rs,char", [(0, 0, 0, False), (1, 1, 1, True), (2, 1, 1, True),
@@ -110,6 +112,7 @@ def test_fp64_ten_steps_sod_32(H, scheme, recon, rs, char):
         one = gpu_step(_dev(ref, torch.float64), dt).cpu().numpy()
         ref = O.step_box(ref, dt, 1 / 32, gamma, scheme, recon, rs, 1, flags)
         assert scaled_max_err(one, ref) <= 1e-12
+        assert var_max_err(one, ref) <= 1e-12
         dev = gpu_step(dev, dt)
     if scheme == 2:
         assert scaled_max_err(dev.cpu().numpy(), ref) <= 1e-4
@@ -183,6 +186,7 @@ def test_ragged_batches_and_empty(H):
                 out, _ = _run(H, G[:n], g, torch.float64, 3e-3, 1 / 48, gamma, scheme, recon, 1, 1, True, plain,
                               False)
                 assert scaled_max_err(out, ref[:n]) <= 1e-12
+                assert var_max_err(out, ref[:n]) <= 1e-12
     z = torch.empty((0, 5, 22, 22, 22), dtype=torch.float32, device="cuda")
     H.solve_groups(z, torch.empty((0, 5, 16, 16, 16), device="cuda"), None, dt=1e-3, dh=1.0, gamma=1.4, scheme=2,
                    recon=1, riemann=1)
@@ -217,6 +221,7 @@ def test_roe_fallback_counted(H):
         out, _ = _run(H, G, g, torch.float64, 2e-3, 1 / 32, gamma, 2, 0, 0, 1, False, plain, False)
         d = H.get_diag(reset=True)
         assert scaled_max_err(out, ref) <= 1e-12
+        assert var_max_err(out, ref) <= 1e-12
         assert d["roe_fallbacks"] >= 1
 
 
@@ -493,6 +498,7 @@ def test_fp64_exact_solver_matches_oracle(H, scheme, recon, char):
     ref, rflux = O.solve_groups(G, g, dt, 1 / 32, gamma, scheme, recon, 3, 1, flags, want_flux=True)
     out, flux = _run(H, G, g, torch.float64, dt, 1 / 32, gamma, scheme, recon, 3, 1, char, False, flux_mid=True)
     assert scaled_max_err(out, ref) <= 1e-12
+    assert var_max_err(out, ref) <= 1e-12
     assert scaled_max_err(flux, rflux) <= 1e-12
 
 
